@@ -1,0 +1,226 @@
+/*
+ * dg.h -- C ABI of the matrix-free SIPG Laplacian library for MI355X (gfx950).
+ *
+ * The operator is the symmetric interior penalty discretisation of
+ * -div(c grad u) from Kronbichler & Kormann, "Fast matrix-free evaluation of
+ * discontinuous Galerkin finite element operators" (arXiv 1711.03590), Sec. 2,
+ * Eq. (2), evaluated as the matrix-vector product y = A u of Sec. 2, Eq. (3)
+ * by the cell/face integration loop of Algorithm 1 with sum factorisation
+ * (Sec. 2, Eqs. (6)-(7); Sec. 3.3, Eq. (8)).
+ *
+ * Discretisation fixed by this library:
+ *   - mesh: structured brick of ncell[0] x ncell[1] x ncell[2] hexahedra on
+ *     the box [lo, hi], optionally deformed by the sine map below;
+ *   - basis: Lagrange polynomials of degree k (1 <= k <= 8) on the k+1
+ *     Gauss-Lobatto points per direction; quadrature: (k+1)-point
+ *     Gauss-Legendre per direction on cells and faces;
+ *   - penalty tau = (k+1)^2 / h_a, h_a the unmapped cell size normal to the face;
+ *   - Dirichlet faces by the mirror principle u+ = -u-, grad u+ = grad u-
+ *     (homogeneous data); Neumann faces (homogeneous) contribute nothing;
+ *   - the coefficient c multiplies the cell term and all three face terms.
+ *
+ * DoF order (all vectors): global = cell * n^3 + i1 + n*i2 + n^2*i3 with
+ * n = k + 1 and cell = cx + ncell[0]*(cy + ncell[1]*cz), i.e. cell-contiguous
+ * blocks in x-fastest order.
+ *
+ * Conventions for every call:
+ *   - every function returns dg_status; DG_OK == 0.  No exception crosses the
+ *     ABI.  dg_last_error() returns a message for the last failure on the
+ *     calling thread (empty string if none).
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device work is enqueued asynchronously on it unless stated otherwise.
+ *   - vectors are dg_vec: a DEVICE pointer owned by the caller, its element
+ *     type and its length.  The caller keeps them alive until the stream work
+ *     that uses them has completed.
+ *   - an op owns its geometry, tables and diagonal, allocated through the
+ *     allocator given at setup (NULL: hipMalloc/hipFree) and released by
+ *     dg_destroy.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DG_OK = 0,
+  DG_ERR_ARG = 1,           /* invalid argument; nothing was enqueued */
+  DG_ERR_OOM = 2,           /* allocation failed */
+  DG_ERR_HIP = 3,           /* a HIP runtime call failed */
+  DG_ERR_UNSUPPORTED = 4,   /* valid but not supported (e.g. degree > 8) */
+  DG_ERR_NOT_CONVERGED = 5  /* solver hit its iteration limit; stats are filled */
+} dg_status;
+
+typedef enum { DG_F64 = 0, DG_F32 = 1 } dg_dtype;
+typedef enum { DG_BC_DIRICHLET = 0, DG_BC_NEUMANN = 1 } dg_bc;
+
+/* Structured brick; bc order x-, x+, y-, y+, z-, z+. */
+typedef struct {
+  int32_t ncell[3];
+  double lo[3], hi[3];
+  int32_t bc[6];
+} dg_mesh;
+
+/* DG_MAP_SINE: x_i = X_i + amplitude * sin(2 pi X) sin(2 pi Y) sin(2 pi Z)
+ * for every component i, X the unmapped point.  Jacobians are precomputed at
+ * every cell and face quadrature point (inverse Jacobian and determinant:
+ * variant G3 of Sec. 5; faces store the normal times inverse Jacobian of
+ * Design Choice 5).  DG_MAP_AFFINE stores no geometry per point (the
+ * constant-Jacobian compression of Sec. 5). */
+typedef enum { DG_MAP_AFFINE = 0, DG_MAP_SINE = 1 } dg_map;
+typedef struct {
+  dg_map map;
+  double amplitude;
+} dg_geometry;
+
+/* DG_COEF_CONST: c = value.  DG_COEF_SINCOS: c = 1 + 0.5 sin(pi x) cos(pi y) z
+ * at the physical point.  A variable coefficient is folded into the stored
+ * quadrature factors (c * det J * w on cells, c * ds on faces). */
+typedef enum { DG_COEF_CONST = 0, DG_COEF_SINCOS = 1 } dg_coef_kind;
+typedef struct {
+  dg_coef_kind kind;
+  double value;
+} dg_coefficient;
+
+/* Device allocator callback pair; ctx is passed through unchanged. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *ctx);
+  void (*free)(void *ptr, void *ctx);
+  void *ctx;
+} dg_allocator;
+
+typedef struct {
+  void *data;     /* device pointer, caller-owned */
+  dg_dtype dtype;
+  int64_t n;      /* number of elements */
+} dg_vec;
+
+typedef struct dg_op dg_op; /* opaque, library-owned */
+
+/* Precision mask for dg_setup / dg_footprint. */
+#define DG_PREC_F64 1u
+#define DG_PREC_F32 2u
+
+/* Bytes of device memory dg_setup will allocate for this problem (geometry,
+ * diagonal, solver workspace excluded).  Pure host computation. */
+dg_status dg_footprint(const dg_mesh *mesh, int degree, const dg_geometry *geom,
+                       const dg_coefficient *coef, unsigned precisions, size_t *bytes);
+
+/* Builds the operator: evaluates the geometry at all quadrature points on the
+ * device (enqueued on stream; the op is usable by later work on the same
+ * stream) and computes the Jacobi diagonal.  The mesh, degree, geometry and
+ * coefficient are the problem statement of Sec. 2 (Eq. (2) with the mapping of
+ * Eq. (4)).  precisions selects which of FP64 / FP32 data to build. */
+dg_status dg_setup(const dg_mesh *mesh, int degree, const dg_geometry *geom,
+                   const dg_coefficient *coef, unsigned precisions, const dg_allocator *alloc,
+                   void *stream, dg_op **out);
+
+/* Number of degrees of freedom (ncells * (k+1)^3); -1 for a NULL op. */
+int64_t dg_n_dofs(const dg_op *op);
+
+/* dst := A src (Sec. 2, Eq. (3)), one fused pass over all cells: each cell
+ * computes its cell integral and the own-side share of its six face integrals
+ * (Algorithm 1, steps (ii)-(iv)) and writes its dst block once; dst need not be
+ * initialised.  src and dst must have the same dtype, which must be enabled in
+ * the op, length dg_n_dofs, and must not alias: otherwise DG_ERR_ARG and nothing
+ * is enqueued. */
+dg_status dg_apply(dg_op *op, dg_vec src, dg_vec dst, void *stream);
+
+/* diag := diagonal of A (in diag.dtype), the Jacobi preconditioner. */
+dg_status dg_diagonal(dg_op *op, dg_vec diag, void *stream);
+
+/* b := load vector of the manufactured solution u* = sin(pi x) sin(pi y) sin(pi z):
+ * b_i = sum_q f(x_q) phi_i(x_q) det J w_q with f = -div(c grad u*). FP64 only. */
+dg_status dg_rhs(dg_op *op, dg_vec b, void *stream);
+
+/* Squared L2 and broken-H1-seminorm errors of the DG function x (FP64)
+ * against u*, by (k+3)-point Gauss quadrature per direction; synchronises
+ * the stream and writes the two square roots to err[0], err[1]. */
+dg_status dg_error_manufactured(dg_op *op, dg_vec x, void *stream, double err[2]);
+
+/* Jacobi-preconditioned conjugate gradients for A x = b.
+ *   mode 0: FP64 CG throughout.
+ *   mode 1: FP32 CG (FP32 applies, FP32 accumulation) on the correction
+ *           equation inside FP64 iterative refinement: r = b - A x in FP64,
+ *           d ~ A^{-1} r in FP32 to rel_tol_inner, x += d in FP64.
+ * Stops when ||b - A x||_2 <= rel_tol * ||b||_2 (always checked with an FP64
+ * apply).  x holds the initial guess on entry.  Synchronises the stream.
+ * Returns DG_ERR_NOT_CONVERGED (stats filled) when the limits are hit. */
+typedef struct {
+  int mode;
+  double rel_tol;
+  double rel_tol_inner;
+  int max_iter;        /* FP64 mode: CG iterations; mixed: inner iterations per refinement step */
+  int max_outer;       /* mixed mode: refinement steps */
+  int check_every;     /* read the residual norm back every this many iterations (>= 1) */
+} dg_solve_params;
+
+typedef struct {
+  int iters_inner;         /* total CG iterations (both modes) */
+  int iters_outer;         /* refinement steps (mixed mode), 0 in FP64 mode */
+  int applies_f64;
+  int applies_f32;
+  double final_rel_residual;
+  double ms;               /* wall time of the call */
+} dg_solve_stats;
+
+dg_status dg_cg_solve(dg_op *op, dg_vec b, dg_vec x, const dg_solve_params *params,
+                      dg_solve_stats *stats, void *stream);
+
+/* Releases everything the op allocated.  Synchronises nothing: the caller
+ * must make sure no enqueued work still uses the op. */
+dg_status dg_destroy(dg_op *op);
+
+const char *dg_last_error(void);
+
+/* Host-only: the 1D tables the kernels are compiled with, for degree k
+ * (1..8), n = k+1.  out receives, in this order: Gauss points (n), Gauss
+ * weights (n), Gauss-Lobatto points (n), S (n*n, S[q][j] = phi_j(gauss_q)),
+ * Dco (n*n, derivative of the Lagrange basis on the Gauss points at the Gauss
+ * points).  len must be >= 3n + 2n^2. */
+dg_status dg_tables(int degree, double *out, size_t len);
+
+/* ---------------------------------------------------------------------------
+ * Continuous batching of solves.  A batch holds up to max_slots solve
+ * requests (mixed precision, the scheme of dg_cg_solve mode 1).  dg_batch_run
+ * advances every active slot: each round is a fixed sequence of launches,
+ * and each launch is ONE persistent kernel that walks a work list of
+ * (slot, cell batch) items covering the cell lists of all active requests,
+ * whatever their degree.  Requests may be admitted while others run.
+ * Results do not depend on which other requests share the batch: every
+ * reduction of a request is done over a fixed partition of its own vector.
+ * ------------------------------------------------------------------------ */
+typedef struct dg_batch dg_batch;
+
+dg_status dg_batch_create(int max_slots, const dg_allocator *alloc, dg_batch **out);
+
+/* Admits a request: op must have both precisions, b and x FP64 of length
+ * dg_n_dofs(op); x holds the initial guess.  The batch allocates the
+ * request's solver workspace (about 8 vectors) through its allocator.
+ * *slot receives the slot index; DG_ERR_OOM if no slot is free. */
+dg_status dg_batch_admit(dg_batch *batch, dg_op *op, dg_vec b, dg_vec x,
+                         const dg_solve_params *params, int *slot, void *stream);
+
+/* Runs up to max_rounds rounds (inner CG iterations) for all active slots on
+ * stream, then synchronises it. */
+dg_status dg_batch_run(dg_batch *batch, int max_rounds, void *stream);
+
+/* Lists slots that finished since the last poll (their x is final) and frees
+ * them; stats[i] belongs to done_slots[i].  capacity bounds both arrays. */
+dg_status dg_batch_poll(dg_batch *batch, int *done_slots, dg_solve_stats *stats, int capacity,
+                        int *n_done);
+
+/* Number of active (admitted, not yet polled) requests. */
+int dg_batch_active(const dg_batch *batch);
+
+dg_status dg_batch_destroy(dg_batch *batch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG_H */

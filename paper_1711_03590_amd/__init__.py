@@ -1,0 +1,278 @@
+"""Matrix-free SIPG Laplacian on MI355X: Python binding of libdg.so.
+
+Argument marshalling only -- every step of the operator runs in the HIP
+kernels behind the C ABI declared in include/dg.h.  PyTorch provides device
+memory (the op's arrays come from torch's caching allocator through the
+allocator callbacks) and streams.  If libdg.so is missing this module raises;
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdg.so")
+
+DG_OK, DG_ERR_ARG, DG_ERR_OOM, DG_ERR_HIP, DG_ERR_UNSUPPORTED, DG_ERR_NOT_CONVERGED = range(6)
+F64, F32 = 0, 1
+DIRICHLET, NEUMANN = 0, 1
+MAP_AFFINE, MAP_SINE = 0, 1
+COEF_CONST, COEF_SINCOS = 0, 1
+PREC_F64, PREC_F32 = 1, 2
+
+
+class DGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"dg status {status}: {msg}")
+        self.status = status
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("ncell", ctypes.c_int32 * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int32 * 6)]
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("map", ctypes.c_int), ("amplitude", ctypes.c_double)]
+
+
+class Coefficient(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("value", ctypes.c_double)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+class Vec(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int), ("n", ctypes.c_int64)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("rel_tol", ctypes.c_double), ("rel_tol_inner", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("max_outer", ctypes.c_int), ("check_every", ctypes.c_int)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters_inner", ctypes.c_int), ("iters_outer", ctypes.c_int),
+                ("applies_f64", ctypes.c_int), ("applies_f32", ctypes.c_int),
+                ("final_rel_residual", ctypes.c_double), ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# (name, restype, argtypes) of every entry point in include/dg.h
+_P = ctypes.c_void_p
+_SIGS = [
+    ("dg_footprint", ctypes.c_int, [ctypes.POINTER(Mesh), ctypes.c_int, ctypes.POINTER(Geometry),
+                                    ctypes.POINTER(Coefficient), ctypes.c_uint, ctypes.POINTER(ctypes.c_size_t)]),
+    ("dg_setup", ctypes.c_int, [ctypes.POINTER(Mesh), ctypes.c_int, ctypes.POINTER(Geometry),
+                                ctypes.POINTER(Coefficient), ctypes.c_uint, ctypes.POINTER(Allocator), _P,
+                                ctypes.POINTER(_P)]),
+    ("dg_n_dofs", ctypes.c_int64, [_P]),
+    ("dg_apply", ctypes.c_int, [_P, Vec, Vec, _P]),
+    ("dg_diagonal", ctypes.c_int, [_P, Vec, _P]),
+    ("dg_rhs", ctypes.c_int, [_P, Vec, _P]),
+    ("dg_error_manufactured", ctypes.c_int, [_P, Vec, _P, ctypes.POINTER(ctypes.c_double)]),
+    ("dg_cg_solve", ctypes.c_int, [_P, Vec, Vec, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveStats), _P]),
+    ("dg_destroy", ctypes.c_int, [_P]),
+    ("dg_last_error", ctypes.c_char_p, []),
+    ("dg_tables", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t]),
+    ("dg_batch_create", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Allocator), ctypes.POINTER(_P)]),
+    ("dg_batch_admit", ctypes.c_int, [_P, _P, Vec, Vec, ctypes.POINTER(SolveParams),
+                                      ctypes.POINTER(ctypes.c_int), _P]),
+    ("dg_batch_run", ctypes.c_int, [_P, ctypes.c_int, _P]),
+    ("dg_batch_poll", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SolveStats), ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_int)]),
+    ("dg_batch_active", ctypes.c_int, [_P]),
+    ("dg_batch_destroy", ctypes.c_int, [_P]),
+]
+
+_lib = None
+
+
+def lib():
+    """The loaded libdg.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no non-HIP fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc):
+    if rc != DG_OK:
+        msg = lib().dg_last_error()
+        raise DGError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def tables(degree):
+    """The compiled-in 1D tables (host only): dict of gauss x/w, gll x, S, Dco."""
+    import numpy as np
+    n = degree + 1
+    out = np.zeros(3 * n + 2 * n * n)
+    check(lib().dg_tables(degree, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size))
+    return {"gx": out[:n], "gw": out[n:2 * n], "lx": out[2 * n:3 * n],
+            "S": out[3 * n:3 * n + n * n].reshape(n, n), "Dco": out[3 * n + n * n:].reshape(n, n)}
+
+
+def make_mesh(ncell, bc=(DIRICHLET,) * 6, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
+    if isinstance(ncell, int):
+        ncell = (ncell,) * 3
+    m = Mesh()
+    m.ncell[:] = list(ncell)
+    m.lo[:] = list(lo)
+    m.hi[:] = list(hi)
+    m.bc[:] = list(bc)
+    return m
+
+
+def footprint(ncell, degree, *, curved=False, amplitude=0.05, variable_coef=False, coef_value=1.0,
+              precisions=PREC_F64 | PREC_F32, bc=(DIRICHLET,) * 6):
+    m = make_mesh(ncell, bc)
+    g = Geometry(MAP_SINE if curved else MAP_AFFINE, amplitude)
+    c = Coefficient(COEF_SINCOS if variable_coef else COEF_CONST, coef_value)
+    out = ctypes.c_size_t()
+    check(lib().dg_footprint(ctypes.byref(m), degree, ctypes.byref(g), ctypes.byref(c), precisions,
+                             ctypes.byref(out)))
+    return out.value
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def vec(t):
+    torch = _torch()
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("vectors must be contiguous device tensors")
+    if t.dtype == torch.float64:
+        dt = F64
+    elif t.dtype == torch.float32:
+        dt = F32
+    else:
+        raise ValueError("vectors must be float64 or float32")
+    return Vec(t.data_ptr(), dt, t.numel())
+
+
+class TorchAllocator:
+    """dg_allocator backed by torch's caching allocator."""
+
+    def __init__(self):
+        torch = _torch()
+        self._dev = torch.cuda.current_device()
+
+        def _alloc(nbytes, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), self._dev)
+            except Exception:
+                return None
+
+        def _free(ptr, ctx):
+            if ptr:
+                torch.cuda.caching_allocator_delete(ptr)
+
+        self._a = ALLOC_FN(_alloc)
+        self._f = FREE_FN(_free)
+        self.struct = Allocator(self._a, self._f, None)
+
+
+class Operator:
+    """One SIPG operator (mesh, degree, geometry, coefficient) resident on the GPU."""
+
+    def __init__(self, ncell, degree, *, curved=False, amplitude=0.05, variable_coef=False, coef_value=1.0,
+                 bc=(DIRICHLET,) * 6, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                 precisions=PREC_F64 | PREC_F32, torch_alloc=True, stream=None):
+        self._h = None
+        self.degree = degree
+        self.mesh = make_mesh(ncell, bc, lo, hi)
+        self.ncell = tuple(self.mesh.ncell)
+        self.curved = curved
+        self.variable_coef = variable_coef
+        self.precisions = precisions
+        self._alloc = TorchAllocator() if torch_alloc else None
+        g = Geometry(MAP_SINE if curved else MAP_AFFINE, amplitude)
+        c = Coefficient(COEF_SINCOS if variable_coef else COEF_CONST, coef_value)
+        h = ctypes.c_void_p()
+        check(lib().dg_setup(ctypes.byref(self.mesh), degree, ctypes.byref(g), ctypes.byref(c), precisions,
+                             ctypes.byref(self._alloc.struct) if self._alloc else None, _stream(stream),
+                             ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n_dofs(self):
+        return int(lib().dg_n_dofs(self._h))
+
+    def apply(self, src, dst=None, stream=None):
+        torch = _torch()
+        if dst is None:
+            dst = torch.empty_like(src)
+        check(lib().dg_apply(self._h, vec(src), vec(dst), _stream(stream)))
+        return dst
+
+    def diagonal(self, dtype=None, stream=None):
+        torch = _torch()
+        d = torch.empty(self.n_dofs, dtype=dtype or torch.float64, device="cuda")
+        check(lib().dg_diagonal(self._h, vec(d), _stream(stream)))
+        return d
+
+    def rhs(self, stream=None):
+        torch = _torch()
+        b = torch.empty(self.n_dofs, dtype=torch.float64, device="cuda")
+        check(lib().dg_rhs(self._h, vec(b), _stream(stream)))
+        return b
+
+    def error_manufactured(self, x, stream=None):
+        err = (ctypes.c_double * 2)()
+        check(lib().dg_error_manufactured(self._h, vec(x), _stream(stream), err))
+        return err[0], err[1]
+
+    def cg_solve(self, b, x=None, *, mixed=True, rel_tol=1e-10, rel_tol_inner=1e-4, max_iter=20000,
+                 max_outer=50, check_every=10, stream=None):
+        torch = _torch()
+        if x is None:
+            x = torch.zeros_like(b)
+        p = SolveParams(1 if mixed else 0, rel_tol, rel_tol_inner, max_iter, max_outer, check_every)
+        st = SolveStats()
+        rc = lib().dg_cg_solve(self._h, vec(b), vec(x), ctypes.byref(p), ctypes.byref(st), _stream(stream))
+        if rc not in (DG_OK, DG_ERR_NOT_CONVERGED):
+            check(rc)
+        out = st.as_dict()
+        out["converged"] = rc == DG_OK
+        return x, out
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().dg_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,100 @@
+// dg_internal.hpp -- shared host/device declarations of the SIPG library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/dg.h"
+
+namespace dgk {
+
+// Geometry representation of an op (Sec. 5):
+//   AFFINE_CONST  constant Jacobian, constant coefficient: nothing stored per point
+//   AFFINE_VAR    constant Jacobian, c * det J * w per cell point, c * ds per face point
+//   CURVED        G3: J^{-T} (9) and c * det J * w per cell point;
+//                 face: j = J^{-1} n (3, Design Choice 5) and c * ds per face point
+enum GeomKind : int { AFFINE_CONST = 0, AFFINE_VAR = 1, CURVED = 2 };
+
+constexpr int kMinN = 2;  // degree 1
+constexpr int kMaxN = 9;  // degree 8
+
+// Per-precision device data of an op.  Cell quantities are stored as
+// separate arrays ("structure of arrays", Sec. 5), each ncells * n^3 long in
+// cell-then-point order; face quantities per direction a, each
+// nfaces[a] * n^2 long, faces of direction a numbered like cells with
+// ncell[a] + 1 planes in that direction.
+template <typename Real>
+struct GeomData {
+  const Real *cell = nullptr;          // CURVED: 10 arrays (J^{-T} row-major, then cJxW); AFFINE_VAR: 1 (cJxW)
+  const Real *face[3] = {nullptr, nullptr, nullptr};  // CURVED: 4 arrays (j0, j1, j2, cds); AFFINE_VAR: 1 (cds)
+  int64_t cell_stride = 0;             // elements between successive quantity arrays
+  int64_t face_stride[3] = {0, 0, 0};
+};
+
+// Everything a kernel needs to know about the problem, passed by value.
+template <typename Real>
+struct OpView {
+  int ncell[3];
+  int ncells;
+  int bc[6];                // 0 Dirichlet, 1 Neumann
+  Real inv_h[3];            // 1 / h_a (affine Jacobian)
+  Real tau[3];              // (k+1)^2 / h_a
+  Real c_vol;               // AFFINE_CONST: c * hx * hy * hz
+  Real c_area[3];           // AFFINE_CONST: c * h_t1 * h_t2 for faces normal to a
+  GeomData<Real> g;
+};
+
+}  // namespace dgk
+
+// The opaque op handle.
+struct dg_op {
+  dg_mesh mesh;
+  int degree = 0, n = 0;
+  dg_geometry geom;
+  dg_coefficient coef;
+  unsigned precisions = 0;
+  int gk = 0;
+  int64_t ncells = 0, ndofs = 0, nfaces[3] = {0, 0, 0};
+  double h[3] = {0, 0, 0};
+  int device = 0;
+  dg_allocator alloc{};
+  bool own_alloc = true;
+  // device allocations (nullptr when absent)
+  void *cell_geo[2] = {nullptr, nullptr};   // [0] FP64, [1] FP32
+  void *face_geo[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  void *diag[2] = {nullptr, nullptr};
+  void *scratch = nullptr;                  // small reduction workspace
+  size_t scratch_bytes = 0;
+  dgk::OpView<double> v64{};
+  dgk::OpView<float> v32{};
+};
+
+namespace dgk {
+
+// error reporting (thread-local message)
+void set_error(const std::string &msg);
+dg_status fail(dg_status st, const std::string &msg);
+dg_status hip_fail(hipError_t e, const char *what);
+
+#define DG_HIP(call)                                        \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return ::dgk::hip_fail(e_, #call); \
+  } while (0)
+
+void *op_alloc(dg_op *op, size_t bytes);
+void op_free(dg_op *op, void *p);
+
+// kernel launchers (one translation unit per n instantiates them)
+template <int N>
+hipError_t launch_apply(const dg_op *op, const void *src, void *dst, bool f32, hipStream_t s);
+template <int N>
+hipError_t launch_diag(const dg_op *op, void *diag64, void *diag32, hipStream_t s);
+
+hipError_t launch_apply_any(const dg_op *op, const void *src, void *dst, bool f32, hipStream_t s);
+hipError_t launch_diag_any(const dg_op *op, void *diag64, void *diag32, hipStream_t s);
+
+}  // namespace dgk

@@ -1,0 +1,87 @@
+"""Host-side checks of libdg.so (no GPU): it loads, exports every symbol
+include/dg.h declares, its compiled-in 1D tables match closed forms, and
+argument validation rejects bad problems before touching the device."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import paper_1711_03590_amd as dg
+    dg.lib()
+    return dg
+
+
+def test_exports_every_declared_symbol(dg):
+    hdr = open(os.path.join(ROOT, "include", "dg.h")).read()
+    names = set(re.findall(r"^\s*(?:dg_status|int64_t|int|const char \*)\s*\**\s*(dg_\w+)\s*\(", hdr, re.M))
+    assert len(names) >= 15
+    L = dg.lib()
+    for n in sorted(names):
+        assert hasattr(L, n), n
+
+
+@pytest.mark.parametrize("k", range(1, 9))
+def test_tables_closed_forms(dg, k):
+    t = dg.tables(k)
+    n = k + 1
+    x, w = t["gx"], t["gw"]
+    for m in range(2 * n):
+        assert np.dot(w, x ** m) == pytest.approx(1.0 / (m + 1), rel=1e-14, abs=1e-15)
+    # Gauss-Lobatto: 0, 1 and the roots of P'_k, i.e. Legendre derivative zeros
+    lx = t["lx"]
+    assert lx[0] == 0.0 and lx[-1] == 1.0
+    if k > 1:
+        dP = np.polynomial.legendre.Legendre.basis(k).deriv()
+        assert np.abs(dP(2 * lx[1:-1] - 1)).max() < 1e-12 * max(1.0, np.abs(dP.coef).max())
+    # S: Lagrange basis on lx at x reproduces polynomials of degree <= k
+    for deg in range(n):
+        assert np.allclose(t["S"] @ lx ** deg, x ** deg, atol=1e-14)
+    # Dco: exact derivative of polynomials of degree < n on the Gauss points
+    for deg in range(n):
+        ref = deg * x ** (deg - 1) if deg > 0 else 0 * x
+        assert np.allclose(t["Dco"] @ x ** deg, ref, atol=1e-12)
+    if n == 3:
+        assert np.allclose(x, [0.5 - 0.5 * math.sqrt(0.6), 0.5, 0.5 + 0.5 * math.sqrt(0.6)], atol=1e-15)
+
+
+def test_tables_symmetry(dg):
+    for k in range(1, 9):
+        t = dg.tables(k)
+        S, D = t["S"], t["Dco"]
+        assert np.abs(S[::-1, ::-1] - S).max() < 1e-14
+        assert np.abs(D[::-1, ::-1] + D).max() < 1e-12 * np.abs(D).max()
+
+
+def test_validation_without_device(dg):
+    with pytest.raises(dg.DGError) as e:
+        dg.footprint(0, 3)
+    assert e.value.status == dg.DG_ERR_ARG
+    with pytest.raises(dg.DGError) as e:
+        dg.footprint(4, 9)
+    assert e.value.status == dg.DG_ERR_UNSUPPORTED
+    with pytest.raises(dg.DGError):
+        dg.footprint(4, 0)
+    with pytest.raises(dg.DGError):
+        dg.footprint(4, 2, precisions=0)
+    with pytest.raises(dg.DGError):
+        dg.footprint(2000, 4)   # more than 2^31-1 DoFs
+
+
+def test_footprint_counts(dg):
+    # curved: 10 values per cell point, 4 per face point, plus the diagonal
+    k, N = 4, 32
+    n = k + 1
+    cells = N ** 3
+    faces = 3 * N * N * (N + 1)
+    vals = 10 * cells * n ** 3 + 4 * faces * n ** 2
+    assert dg.footprint(N, k, curved=True, precisions=dg.PREC_F64) == vals * 8 + cells * n ** 3 * 8
+    assert dg.footprint(N, k, precisions=dg.PREC_F64 | dg.PREC_F32) == cells * n ** 3 * 12
+    assert dg.footprint(N, k, variable_coef=True, precisions=dg.PREC_F32) == \
+        (cells * n ** 3 + faces * n ** 2) * 4 + cells * n ** 3 * 4
