@@ -1,0 +1,228 @@
+"""Benchmark of the matrix-free SIPG apply on one MI355X.
+
+Workload: 32^3 hexahedra on the unit cube deformed by the sine map
+(amplitude 0.05), degree k = 4 (4,096,000 DoFs), Jacobians stored at every
+quadrature point, seeded uniform [-1,1] source.  A step is one operator
+evaluation y = A u over the whole mesh (the fused cell + face pass).  The
+headline value is FP64 DoF/s; the FP32 apply and, when requested, the
+mixed-precision solve latency of the manufactured-solution Poisson problem
+are reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--solve-reps R] [--only f64|f32] [--copy-calibration MB]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SIPG apply DoF/s (FP64 vs FP32, k=4 curved); mixed-prec solve p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1711_03590_amd", "csrc", "kernels.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sipg_apply_f64_curved_k4_32cubed_traffic.txt")
+
+
+def algorithmic_bytes_per_dof(ncell, k, real_bytes):
+    """src read + dst write + every stored geometry value read once:
+    10 per cell quadrature point (J^{-T}, c det J w), 4 per face quadrature
+    point (n.J^{-1}, c ds); neighbour re-reads and tables not counted."""
+    n = k + 1
+    cells = ncell ** 3
+    faces = 3 * ncell * ncell * (ncell + 1)
+    vals = 2 * cells * n ** 3 + 10 * cells * n ** 3 + 4 * faces * n * n
+    return vals * real_bytes / (cells * n ** 3)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
+
+
+def measured_traffic(dtype):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m = re.search(r"kernel_source_sha1:\s*(\w+)", txt)
+    if not m or m.group(1) != kernel_hash():
+        return None
+    m = re.search(rf"{dtype}_hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    return float(m.group(1)) if m else None
+
+
+def time_apply(op, x, y, steps, warmup, torch):
+    for _ in range(warmup):
+        op.apply(x, y)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        op.apply(x, y)
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def cpu_baseline(ncell, k, budget_s=12.0):
+    """The oracle (plain FP64 quadrature, OpenMP) on a bounded sample of the
+    same workload: the first cells of the mesh, repeated until the budget is
+    spent; DoF/s over the processed cells."""
+    import numpy as np
+    import oracle
+    import synth
+    p = oracle.problem(ncell, k, curved=True)
+    nd = oracle.n_dofs(p)
+    src = synth.src_vector(nd, synth.seed_for(2, k))
+    cells = np.arange(min(4096, ncell ** 3), dtype=np.int64)
+    n3 = (k + 1) ** 3
+    oracle.apply_cells(p, src, cells[:64])  # warm up tables and threads
+    done, t0 = 0, time.perf_counter()
+    while True:
+        oracle.apply_cells(p, src, cells)
+        done += len(cells)
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": done * n3 / el, "unit": "DoF/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{len(cells)} cells ({len(cells) * n3} DoFs) of the 32^3 curved k=4 mesh, "
+                      f"applied {done // len(cells)} times in {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--ncell", type=int, default=32)
+    ap.add_argument("--degree", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["f64", "f32"], default=None)
+    ap.add_argument("--solve-reps", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one MI355X; runs on more than one GPU are not "
+              "supported (the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1711_03590_amd as dg
+    import synth
+
+    torch.cuda.set_device(0)
+    k, N = args.degree, args.ncell
+    op = dg.Operator(N, k, curved=True, amplitude=synth.AMPLITUDE)
+    nd = op.n_dofs
+    src = synth.src_vector(nd, synth.seed_for(2, k))
+    res = {}
+    for prec in ("f64", "f32"):
+        if args.only and prec != args.only:
+            continue
+        dt = torch.float64 if prec == "f64" else torch.float32
+        x = torch.from_numpy(src).to(dtype=dt, device="cuda")
+        y = torch.empty_like(x)
+        ms = time_apply(op, x, y, args.steps, args.warmup, torch)
+        bpd = algorithmic_bytes_per_dof(N, k, 8 if prec == "f64" else 4)
+        achieved = bpd * nd / (ms * 1e-3) / 1e9
+        traffic = measured_traffic(prec)
+        res[prec] = dict(ms=ms, dofs=nd / (ms * 1e-3), bytes_per_dof=bpd, achieved_gbs=achieved,
+                         frac=achieved / HBM_PEAK_GBS, traffic=traffic)
+        del x, y
+
+    if args.copy_calibration:
+        nel = args.copy_calibration * (1 << 20) // 8
+        a = torch.ones(nel, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
+
+    solve = None
+    if args.solve_reps > 0:
+        solve = bench_solve(dg, torch, np, synth, args.solve_reps)
+
+    head = res.get("f64") or res.get("f32")
+    headp = "f64" if "f64" in res else "f32"
+    line = {
+        "metric": METRIC,
+        "value": head["dofs"],
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": headp,
+        "data": "synthetic: seeded uniform [-1,1] source on a generated mesh",
+        "config": {"workload": f"SIPG Laplacian apply, {N}^3 sine-curved hex mesh (amplitude 0.05), "
+                               f"degree k={k}, G3 geometry at every quadrature point, {nd} DoFs",
+                   "ncell": N, "degree": k, "n_dofs": nd, "geometry": "curved-G3"},
+        "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": head["frac"],
+                     "traffic": head["traffic"],
+                     "algorithmic_bytes_per_dof": head["bytes_per_dof"],
+                     "kernel": f"sipg_apply_kernel<{k + 1}, {'double' if headp == 'f64' else 'float'}, CURVED>"},
+    }
+    if "f32" in res and headp == "f64":
+        r = res["f32"]
+        line["fp32"] = {"value": r["dofs"], "ms_per_step": r["ms"], "achieved_gbs": r["achieved_gbs"],
+                        "frac": r["frac"], "traffic": r["traffic"], "algorithmic_bytes_per_dof": r["bytes_per_dof"],
+                        "speedup_vs_fp64": r["dofs"] / head["dofs"]}
+    if solve:
+        line["solve"] = solve
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(N, k)
+    print(json.dumps(line), flush=True)
+    op.close()
+
+
+def bench_solve(dg, torch, np, synth, reps):
+    """Manufactured Poisson solve on the 32^3 curved mesh, k=5, variable c:
+    mixed (FP32 CG inside FP64 refinement) and pure FP64 CG to 1e-10."""
+    op = dg.Operator(32, 5, curved=True, variable_coef=True)
+    b = op.rhs()
+    out = {}
+    for mode in ("mixed", "fp64"):
+        times, last = [], None
+        for r in range(reps + 1):
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, st = op.cg_solve(b, x, mixed=(mode == "mixed"), rel_tol=1e-10)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) * 1e3
+            if r > 0:
+                times.append(el)
+            last = (x, st)
+        x, st = last
+        l2, h1 = op.error_manufactured(x)
+        t = np.array(times)
+        out[mode] = {"p50_ms": float(np.percentile(t, 50)), "p99_ms": float(np.percentile(t, 99)),
+                     "reps": reps, "converged": st["converged"], "iters_inner": st["iters_inner"],
+                     "iters_outer": st["iters_outer"], "applies_f64": st["applies_f64"],
+                     "applies_f32": st["applies_f32"], "final_rel_residual": st["final_rel_residual"],
+                     "l2_error_vs_exact": l2}
+    out["workload"] = "32^3 curved, k=5 (7,077,888 DoFs), c = 1 + 0.5 sin(pi x) cos(pi y) z, to 1e-10"
+    out["speedup_mixed_vs_fp64_p50"] = out["fp64"]["p50_ms"] / out["mixed"]["p50_ms"]
+    op.close()
+    return out
+
+
+if __name__ == "__main__":
+    main()

@@ -45,32 +45,32 @@ template <int N>
 inline constexpr EvenOdd<N> kEoDco = make_even_odd<N>(kTab<N>.Dco, false);
 template <int N>
 inline constexpr EvenOdd<N> kEoDcot = make_even_odd<N>(kTab<N>.Dco, true);
+template <int N>
+inline constexpr EvenOdd<N> kEoD = make_even_odd<N>(kTab<N>.D, false);
 
-enum : int { M_S = 0, M_ST = 1, M_DCO = 2, M_DCOT = 3 };
+enum : int { M_S = 0, M_ST = 1, M_DCO = 2, M_DCOT = 3, M_D = 4 };
 
-template <int N, int M>
-__device__ __forceinline__ constexpr double eo_E(int i, int j)
+// acc + c x with c a compile-time constant after unrolling: zero and unit
+// coefficients fold away (accumulators start at -0.0, the additive identity)
+template <typename Real>
+__device__ __forceinline__ Real madd(double c, Real x, Real acc)
 {
-  if constexpr (M == M_S) return kEoS<N>.E[i][j];
-  else if constexpr (M == M_ST) return kEoSt<N>.E[i][j];
-  else if constexpr (M == M_DCO) return kEoDco<N>.E[i][j];
-  else return kEoDcot<N>.E[i][j];
+  if (c == 0.0) return acc;
+  if (c == 1.0) return acc + x;
+  if (c == -1.0) return acc - x;
+  return fma(Real(c), x, acc);
 }
+
+// the even-odd table of matrix M (as a value, so that every use below is a
+// compile-time constant once the loops are unrolled)
 template <int N, int M>
-__device__ __forceinline__ constexpr double eo_O(int i, int j)
+__host__ __device__ constexpr EvenOdd<N> eo_tab()
 {
-  if constexpr (M == M_S) return kEoS<N>.O[i][j];
-  else if constexpr (M == M_ST) return kEoSt<N>.O[i][j];
-  else if constexpr (M == M_DCO) return kEoDco<N>.O[i][j];
-  else return kEoDcot<N>.O[i][j];
-}
-template <int N, int M>
-__device__ __forceinline__ constexpr double eo_Mid(int i)
-{
-  if constexpr (M == M_S) return kEoS<N>.Mid[i];
-  else if constexpr (M == M_ST) return kEoSt<N>.Mid[i];
-  else if constexpr (M == M_DCO) return kEoDco<N>.Mid[i];
-  else return kEoDcot<N>.Mid[i];
+  if constexpr (M == M_S) return kEoS<N>;
+  else if constexpr (M == M_ST) return kEoSt<N>;
+  else if constexpr (M == M_DCO) return kEoDco<N>;
+  else if constexpr (M == M_DCOT) return kEoDcot<N>;
+  else return kEoD<N>;
 }
 
 // out = M in for one line of N values, M one of S, S^T (centro-symmetric) or
@@ -81,6 +81,7 @@ __device__ __forceinline__ void eo_apply(const Real (&in)[N], Real (&out)[N])
 {
   constexpr int H = N / 2;
   constexpr bool sym = (M == M_S || M == M_ST);
+  constexpr EvenOdd<N> C = eo_tab<N, M>();
   Real e[H > 0 ? H : 1], o[H > 0 ? H : 1];
 #pragma unroll
   for (int j = 0; j < H; ++j) {
@@ -89,29 +90,27 @@ __device__ __forceinline__ void eo_apply(const Real (&in)[N], Real (&out)[N])
   }
 #pragma unroll
   for (int i = 0; i < H; ++i) {
-    Real se = Real(eo_E<N, M>(i, 0)) * e[0];
-    Real so = Real(eo_O<N, M>(i, 0)) * o[0];
+    Real se = Real(-0.0), so = Real(-0.0);
 #pragma unroll
-    for (int j = 1; j < H; ++j) {
-      se = fma(Real(eo_E<N, M>(i, j)), e[j], se);
-      so = fma(Real(eo_O<N, M>(i, j)), o[j], so);
+    for (int j = 0; j < H; ++j) {
+      se = madd(C.E[i][j], e[j], se);
+      so = madd(C.O[i][j], o[j], so);
     }
-    if constexpr (N % 2 == 1) se = fma(Real(eo_Mid<N, M>(i)), in[H], se);
+    if constexpr (N % 2 == 1) se = madd(C.Mid[i], in[H], se);
     out[i] = se + so;
     out[N - 1 - i] = sym ? se - so : so - se;
   }
   if constexpr (N % 2 == 1) {
+    Real s = Real(-0.0);
     if constexpr (sym) {
-      Real s = Real(eo_Mid<N, M>(H)) * in[H];
+      s = madd(C.Mid[H], in[H], s);
 #pragma unroll
-      for (int j = 0; j < H; ++j) s = fma(Real(eo_E<N, M>(H, j)), e[j], s);
-      out[H] = s;
+      for (int j = 0; j < H; ++j) s = madd(C.E[H][j], e[j], s);
     } else {
-      Real s = Real(0);
 #pragma unroll
-      for (int j = 0; j < H; ++j) s = fma(Real(eo_O<N, M>(H, j)), o[j], s);
-      out[H] = s;
+      for (int j = 0; j < H; ++j) s = madd(C.O[H][j], o[j], s);
     }
+    out[H] = s;
   }
 }
 
@@ -150,19 +149,22 @@ __device__ __forceinline__ void sweep(const Real *in, Real *out, int l)
   store_line<N, A>(out, l, r);
 }
 
-// sum_m L[m] v[m] for the two ends at once (L1[m] = L0[N-1-m] by symmetry)
+// values at xi = 0 and xi = 1 of the polynomial with Gauss-point values v:
+// sum_m L0[m] v[m] and sum_m L1[m] v[m], with L1[m] = L0[N-1-m]
 template <int N, typename Real>
 __device__ __forceinline__ void end_values(const Real (&v)[N], Real &lo, Real &hi)
 {
-  constexpr const auto &T = kTab<N>;
-  Real a = Real(T.L0[0]) * v[0], b = Real(T.L1[0]) * v[0];
+  constexpr Tables<N> T = kTab<N>;
+  constexpr int H = N / 2;
+  Real se = Real(-0.0), so = Real(-0.0);
 #pragma unroll
-  for (int m = 1; m < N; ++m) {
-    a = fma(Real(T.L0[m]), v[m], a);
-    b = fma(Real(T.L1[m]), v[m], b);
+  for (int m = 0; m < H; ++m) {
+    se = madd(0.5 * (T.L0[m] + T.L0[N - 1 - m]), v[m] + v[N - 1 - m], se);
+    so = madd(0.5 * (T.L0[m] - T.L0[N - 1 - m]), v[m] - v[N - 1 - m], so);
   }
-  lo = a;
-  hi = b;
+  if constexpr (N % 2 == 1) se = madd(T.L0[H], v[H], se);
+  lo = se + so;
+  hi = se - so;
 }
 
 // consecutive workgroups are dispatched round-robin over the 8 XCDs; give
@@ -181,7 +183,25 @@ struct Blocking {
   static constexpr int N2 = N * N, N3 = N2 * N;
   static constexpr int B = 256 / N2;         // cells per workgroup
   static constexpr int NT = B * N2;          // active threads
-  static constexpr int WSZ = (3 * N3 > 14 * N2) ? 3 * N3 : 14 * N2;  // gradient / face scratch per cell
+  static constexpr int WSZ = (2 * N3 > 10 * N2) ? 2 * N3 : 10 * N2;  // gradient / face scratch per cell
+};
+
+// Workgroups per CU that the LDS footprint allows (160 KiB per CU).  With
+// 256-thread workgroups this is also the number of waves per SIMD, which is
+// passed to the compiler as the occupancy target so that register
+// allocation does not become the tighter limit.
+#ifndef DG_MAX_WAVES_F64
+#define DG_MAX_WAVES_F64 4
+#endif
+#ifndef DG_MAX_WAVES_F32
+#define DG_MAX_WAVES_F32 5
+#endif
+template <int N, typename Real>
+struct Occupancy {
+  static constexpr int lds = Blocking<N>::B * (2 * Blocking<N>::N3 + Blocking<N>::WSZ) * (int)sizeof(Real);
+  static constexpr int wgs = 163840 / lds;
+  static constexpr int cap = sizeof(Real) == 8 ? DG_MAX_WAVES_F64 : DG_MAX_WAVES_F32;
+  static constexpr int value = wgs < 1 ? 1 : (wgs > cap ? cap : wgs);
 };
 
 // face index of the face of cell ci on side s of direction A
@@ -195,46 +215,113 @@ __device__ __forceinline__ int64_t face_id(const int (&nc)[3], const int (&ci)[3
   return p[0] + (int64_t)m[0] * (p[1] + (int64_t)m[1] * p[2]);
 }
 
-// Face terms of direction A for the cell owned by this thread's group.
-// tr[s][0..3]: own value and reference gradient (x,y,z) at face point l of
-// the face on side s (0: xi_A = 0, 1: xi_A = 1).
+// geometry of face point l of the face of cell ci on side s of direction A:
+// j = J^{-1} n for the normal pointing along +e_A, and c ds
+template <int N, typename Real, int GK, int A>
+__device__ __forceinline__ void face_geometry(const OpView<Real> &op, const int (&ci)[3], int s, int l,
+                                              Real (&j)[3], Real &cds)
+{
+  constexpr int N2 = N * N;
+  constexpr Tables<N> T = kTab<N>;
+  j[0] = j[1] = j[2] = Real(0);
+  if constexpr (GK == CURVED) {
+    const int64_t f = face_id<A>(op.ncell, ci, s) * N2 + l;
+    const Real *fg = op.g.face[A];
+    const int64_t fs = op.g.face_stride[A];
+    j[0] = fg[f];
+    j[1] = fg[fs + f];
+    j[2] = fg[2 * fs + f];
+    cds = fg[3 * fs + f];
+  } else if constexpr (GK == AFFINE_VAR) {
+    j[A] = op.inv_h[A];
+    cds = op.g.face[A][face_id<A>(op.ncell, ci, s) * N2 + l];
+  } else {
+    j[A] = op.inv_h[A];
+    const int q1 = l % N, q2 = l / N;
+    Real w1 = Real(0), w2 = Real(0);
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      if (q == q1) w1 = Real(T.gw[q]);
+      if (q == q2) w2 = Real(T.gw[q]);
+    }
+    cds = op.c_area[A] * w1 * w2;
+  }
+}
+
+// sum_m dL0[m] v[m] and sum_m dL1[m] v[m]: derivatives at xi = 0, 1 of the
+// polynomial with Gauss-point values v (dL1[m] = -dL0[N-1-m])
+template <int N, typename Real>
+__device__ __forceinline__ void end_derivatives(const Real (&v)[N], Real &lo, Real &hi)
+{
+  constexpr Tables<N> T = kTab<N>;
+  constexpr int H = N / 2;
+  Real se = Real(-0.0), so = Real(-0.0);
+#pragma unroll
+  for (int m = 0; m < H; ++m) {
+    se = madd(0.5 * (T.dL0[m] + T.dL0[N - 1 - m]), v[m] + v[N - 1 - m], se);
+    so = madd(0.5 * (T.dL0[m] - T.dL0[N - 1 - m]), v[m] - v[N - 1 - m], so);
+  }
+  if constexpr (N % 2 == 1) se = madd(T.dL0[H], v[H], se);
+  lo = se + so;
+  hi = so - se;
+}
+
+// Face terms of direction A for this thread group's cell: the face integrals
+// of Sec. 2 Eq. (2) over the cell's two faces normal to A, own side only
+// (the element's share of Algorithm 1 steps (iii)-(iv)), added into the
+// quadrature-point residual R along the normal lines.  Q holds the cell's
+// values at the Gauss points; W is 10 N^2 of scratch.
+//   [[u]] = u- - u+, {{grad u}} = (grad u- + grad u+)/2; the average's
+//   tangential part is the tangential derivative of V = u- + u+ on the face
+//   (V = 2 u- on a Dirichlet face, where u+ = -u- but grad u+ = grad u-).
 template <int N, typename Real, int GK, int A>
 __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Real *__restrict__ src,
-                                               Real *Q, Real *W, int l, int cell, const int (&ci)[3],
-                                               bool act, bool valid, const Real (&tr)[2][4])
+                                               const Real *Q, Real *R, Real *W, int l, int cell,
+                                               const int (&ci)[3], bool act, bool valid)
 {
   constexpr int N2 = N * N, N3 = N2 * N;
   constexpr int t1 = (A == 0) ? 1 : 0, t2 = (A == 2) ? 1 : 2;
-  constexpr const auto &T = kTab<N>;
-  Real *X = W;            // [side][value, normal derivative][N2] at Gauss-Lobatto face nodes
-  Real *Y = W + 4 * N2;   // [side][S u, D u, S d][N2] after the sweep along t1
-  Real *Z = W + 10 * N2;  // [side][tg_t1, tg_t2][N2]
+  constexpr Tables<N> T = kTab<N>;
+  Real *X = W;            // [s][value, normal derivative] of the neighbour at Gauss-Lobatto face nodes p1 + N p2
+  Real *Y = W + 4 * N2;   // [s][..] after the basis change along t1: q1 + N p2
+  Real *U = W;            // [s][u+, d_A u+] at the face Gauss points q1 + N q2
+  Real *V = W + 8 * N2;   // [s] u- + u+
+  Real *dV = W + 4 * N2;  // [s][d_t1 V, d_t2 V]
+  Real *Z = W;            // [s][tg_t1, tg_t2]
+  Real *Z2 = W + 4 * N2;  // [s][Dco^T along t1 of tg_t1 + ..., Dco^T along t2 of tg_t2]
   const int64_t cstride = (A == 0) ? 1 : (A == 1 ? (int64_t)op.ncell[0] : (int64_t)op.ncell[0] * op.ncell[1]);
-  bool interior[2] = {false, false};
+  bool interior[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const int cn = ci[A] + (s ? 1 : -1);
     interior[s] = valid && cn >= 0 && cn < op.ncell[A];
   }
-  // (1) neighbour traces at the Gauss-Lobatto nodes of the shared face
+  // S1: own value and reference normal derivative at this face point (the
+  // Gauss-point data is tangentially at the face's Gauss points already);
+  // the neighbour's value and normal derivative at the Gauss-Lobatto nodes of
+  // the shared face: end node (nodal basis) and D_f of Eq. (7)
+  Real um[2], dm[2];
   if (act) {
+    Real v[N];
+    load_line<N, A>(Q, l, v);
+    end_values<N>(v, um[0], um[1]);
+    end_derivatives<N>(v, dm[0], dm[1]);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       Real val = Real(0), der = Real(0);
       if (interior[s]) {
         const Real *nb = src + (int64_t)(cell + (s ? cstride : -cstride)) * N3;
-        Real v[N];
-        load_line<N, A>(nb, l, v);
-        if (s == 0) {  // neighbour below: shared face is its xi_A = 1 side
-          val = v[N - 1];
-          der = Real(T.F1[0]) * v[0];
+        Real w[N];
+        load_line<N, A>(nb, l, w);
+        der = Real(-0.0);
+        if (s == 0) {  // neighbour below: the shared face is its xi_A = 1 side
+          val = w[N - 1];
 #pragma unroll
-          for (int m = 1; m < N; ++m) der = fma(Real(T.F1[m]), v[m], der);
+          for (int m = 0; m < N; ++m) der = madd(T.F1[m], w[m], der);
         } else {       // neighbour above: its xi_A = 0 side
-          val = v[0];
-          der = Real(T.F0[0]) * v[0];
+          val = w[0];
 #pragma unroll
-          for (int m = 1; m < N; ++m) der = fma(Real(T.F0[m]), v[m], der);
+          for (int m = 0; m < N; ++m) der = madd(T.F0[m], w[m], der);
         }
       }
       X[(2 * s) * N2 + l] = val;
@@ -242,174 +329,130 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
     }
   }
   __syncthreads();
-  // (2) sweep along t1: S and D on the values, S on the normal derivatives
-  if (act) {
-    const int q1 = l % N, p2 = l / N;
-    Real srow[N], drow[N];
+  // S2: neighbour traces, basis change along t1 (one line per job)
+  // (2N jobs; with N^2 < 2N threads per cell a thread takes several)
+  if (act) for (int jb = l; jb < 2 * N; jb += N2) {
+    const int s = jb / N, p2 = jb - s * N;
+    Real v[N], r[N];
 #pragma unroll
-    for (int m = 0; m < N; ++m) {
-      srow[m] = Real(0);
-      drow[m] = Real(0);
+    for (int f = 0; f < 2; ++f) {
 #pragma unroll
-      for (int q = 0; q < N; ++q)
-        if (q == q1) { srow[m] = Real(T.S[q][m]); drow[m] = Real(T.D[q][m]); }
-    }
+      for (int m = 0; m < N; ++m) v[m] = X[(2 * s + f) * N2 + m + N * p2];
+      eo_apply<N, M_S>(v, r);
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const Real *xv = X + (2 * s) * N2 + N * p2;
-      const Real *xd = X + (2 * s + 1) * N2 + N * p2;
-      Real su = Real(0), du = Real(0), sd = Real(0);
-#pragma unroll
-      for (int m = 0; m < N; ++m) {
-        su = fma(srow[m], xv[m], su);
-        du = fma(drow[m], xv[m], du);
-        sd = fma(srow[m], xd[m], sd);
-      }
-      Y[(3 * s) * N2 + l] = su;
-      Y[(3 * s + 1) * N2 + l] = du;
-      Y[(3 * s + 2) * N2 + l] = sd;
+      for (int m = 0; m < N; ++m) Y[(2 * s + f) * N2 + m + N * p2] = r[m];
     }
   }
   __syncthreads();
-  // (3) sweep along t2, numerical flux at face point l
-  Real tv[2] = {Real(0), Real(0)}, tga[2] = {Real(0), Real(0)};
-  if (act) {
-    const int q1 = l % N, q2 = l / N;
-    Real srow[N], drow[N];
+  // S3: basis change along t2
+  if (act) for (int jb = l; jb < 2 * N; jb += N2) {
+    const int s = jb / N, q1 = jb - s * N;
+    Real v[N], r[N];
 #pragma unroll
-    for (int m = 0; m < N; ++m) {
-      srow[m] = Real(0);
-      drow[m] = Real(0);
+    for (int f = 0; f < 2; ++f) {
 #pragma unroll
-      for (int q = 0; q < N; ++q)
-        if (q == q2) { srow[m] = Real(T.S[q][m]); drow[m] = Real(T.D[q][m]); }
+      for (int m = 0; m < N; ++m) v[m] = Y[(2 * s + f) * N2 + q1 + N * m];
+      eo_apply<N, M_S>(v, r);
+#pragma unroll
+      for (int m = 0; m < N; ++m) U[(2 * s + f) * N2 + q1 + N * m] = r[m];
     }
+  }
+  __syncthreads();
+  // S4: jump, sum of values, sum of normal reference derivatives
+  Real jump[2] = {Real(0), Real(0)}, dsum[2] = {Real(0), Real(0)};
+  if (act) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      Real up = Real(0), gp[3] = {Real(0), Real(0), Real(0)};
-      {
-        const Real *y0 = Y + (3 * s) * N2 + q1;
-        const Real *y1 = Y + (3 * s + 1) * N2 + q1;
-        const Real *y2 = Y + (3 * s + 2) * N2 + q1;
-#pragma unroll
-        for (int m = 0; m < N; ++m) {
-          up = fma(srow[m], y0[N * m], up);
-          gp[t2] = fma(drow[m], y0[N * m], gp[t2]);
-          gp[t1] = fma(srow[m], y1[N * m], gp[t1]);
-          gp[A] = fma(srow[m], y2[N * m], gp[A]);
-        }
+      Real up, dp;
+      if (interior[s]) {
+        up = U[(2 * s) * N2 + l];
+        dp = U[(2 * s + 1) * N2 + l];
+      } else {  // Dirichlet mirror u+ = -u-, grad u+ = grad u-
+        up = -um[s];
+        dp = dm[s];
       }
-      // geometry at this face point (normal of direction +e_A)
+      jump[s] = um[s] - up;
+      dsum[s] = dm[s] + dp;
+      V[s * N2 + l] = interior[s] ? um[s] + up : Real(2) * um[s];
+    }
+  }
+  __syncthreads();
+  // S5: tangential collocation derivatives of V (lines along t1 and t2)
+  if (act) for (int jb = l; jb < 4 * N; jb += N2) {
+    const int s = jb / (2 * N), c = (jb / N) & 1, i = jb % N;
+    const int base = c ? i : N * i, stride = c ? N : 1;
+    Real v[N], r[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = V[s * N2 + base + m * stride];
+    eo_apply<N, M_DCO>(v, r);
+#pragma unroll
+    for (int m = 0; m < N; ++m) dV[(2 * s + c) * N2 + base + m * stride] = r[m];
+  }
+  __syncthreads();
+  // S6: numerical flux at this face point (Algorithm 1 step (c) for faces)
+  Real tv[2] = {Real(0), Real(0)}, tga[2] = {Real(0), Real(0)};
+  if (act) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
       Real j[3] = {Real(0), Real(0), Real(0)}, cds = Real(0);
-      if (valid) {
-        if constexpr (GK == CURVED) {
-          const int64_t f = face_id<A>(op.ncell, ci, s) * N2 + l;
-          const Real *fg = op.g.face[A];
-          const int64_t fs = op.g.face_stride[A];
-          j[0] = fg[f];
-          j[1] = fg[fs + f];
-          j[2] = fg[2 * fs + f];
-          cds = fg[3 * fs + f];
-        } else if constexpr (GK == AFFINE_VAR) {
-          const int64_t f = face_id<A>(op.ncell, ci, s) * N2 + l;
-          j[A] = op.inv_h[A];
-          cds = op.g.face[A][f];
-        } else {
-          j[A] = op.inv_h[A];
-          Real w1 = Real(0), w2 = Real(0);
-#pragma unroll
-          for (int q = 0; q < N; ++q) {
-            if (q == q1) w1 = Real(T.gw[q]);
-            if (q == q2) w2 = Real(T.gw[q]);
-          }
-          cds = op.c_area[A] * w1 * w2;
-        }
-      }
+      if (valid) face_geometry<N, Real, GK, A>(op, ci, s, l, j, cds);
+      if (!interior[s] && op.bc[2 * A + s] != 0) cds = Real(0);  // homogeneous Neumann
       const Real sg = s ? Real(1) : Real(-1);
       const Real je[3] = {sg * j[0], sg * j[1], sg * j[2]};
-      const Real um = tr[s][0];
-      const Real dnm = je[0] * tr[s][1] + je[1] * tr[s][2] + je[2] * tr[s][3];
-      Real uplus, dnp;
-      if (interior[s]) {
-        uplus = up;
-        dnp = je[0] * gp[0] + je[1] * gp[1] + je[2] * gp[2];
-      } else {  // boundary: Dirichlet mirror; Neumann contributes nothing
-        uplus = -um;
-        dnp = dnm;
-        if (op.bc[2 * A + s] != 0) cds = Real(0);
-      }
-      const Real jump = um - uplus;
-      const Real avg = Real(0.5) * (dnm + dnp);
-      tv[s] = cds * (op.tau[A] * jump - avg);
-      const Real gfac = Real(-0.5) * cds * jump;
+      Real g[3];
+      g[t1] = dV[(2 * s) * N2 + l];
+      g[t2] = dV[(2 * s + 1) * N2 + l];
+      g[A] = dsum[s];
+      const Real avg = Real(0.5) * (je[0] * g[0] + je[1] * g[1] + je[2] * g[2]);
+      tv[s] = cds * (op.tau[A] * jump[s] - avg);
+      const Real gfac = Real(-0.5) * cds * jump[s];
       tga[s] = gfac * je[A];
       Z[(2 * s) * N2 + l] = gfac * je[t1];
       Z[(2 * s + 1) * N2 + l] = gfac * je[t2];
     }
   }
   __syncthreads();
-  // (4) transposed tangential collocation derivatives of the gradient-test
-  // terms, then add the face contributions along this thread's normal line
+  // S7: transposed tangential collocation derivatives of the gradient-test terms
+  if (act) for (int jb = l; jb < 4 * N; jb += N2) {
+    const int s = jb / (2 * N), c = (jb / N) & 1, i = jb % N;
+    const int base = c ? i : N * i, stride = c ? N : 1;
+    Real v[N], r[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = Z[(2 * s + c) * N2 + base + m * stride];
+    eo_apply<N, M_DCOT>(v, r);
+#pragma unroll
+    for (int m = 0; m < N; ++m) Z2[(2 * s + c) * N2 + base + m * stride] = r[m];
+  }
+  __syncthreads();
+  // S8: face-normal integration onto this thread's normal line of R
   if (act) {
-    const int p1 = l % N, p2 = l / N;
     Real w[2];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      Real acc = tv[s];
-      const Real *z1 = Z + (2 * s) * N2 + N * p2;
-      const Real *z2 = Z + (2 * s + 1) * N2 + p1;
-#pragma unroll
-      for (int q = 0; q < N; ++q) {
-        Real d1 = Real(0), d2 = Real(0);
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-          if (r == p1) d1 = Real(T.Dco[q][r]);
-          if (r == p2) d2 = Real(T.Dco[q][r]);
-        }
-        acc = fma(d1, z1[q], acc);
-        acc = fma(d2, z2[N * q], acc);
-      }
-      w[s] = acc;
-    }
+    for (int s = 0; s < 2; ++s) w[s] = tv[s] + Z2[(2 * s) * N2 + l] + Z2[(2 * s + 1) * N2 + l];
     Real r[N];
-    load_line<N, A>(Q, l, r);
+    load_line<N, A>(R, l, r);
 #pragma unroll
     for (int m = 0; m < N; ++m) {
       Real v = r[m];
-      v = fma(Real(T.L0[m]), w[0], v);
+      v = madd(T.L0[m], w[0], v);
       v = fma(Real(T.dL0[m]), tga[0], v);
-      v = fma(Real(T.L1[m]), w[1], v);
+      v = madd(T.L1[m], w[1], v);
       v = fma(Real(T.dL1[m]), tga[1], v);
       r[m] = v;
     }
-    store_line<N, A>(Q, l, r);
+    store_line<N, A>(R, l, r);
   }
   __syncthreads();
 }
 
-template <int N, typename Real, int A>
-__device__ __forceinline__ void own_traces(const Real *Q, const Real *G0, const Real *G1,
-                                           const Real *G2, int l, Real (&tr)[2][4])
-{
-  Real v[N];
-  load_line<N, A>(Q, l, v);
-  end_values<N>(v, tr[0][0], tr[1][0]);
-  load_line<N, A>(G0, l, v);
-  end_values<N>(v, tr[0][1], tr[1][1]);
-  load_line<N, A>(G1, l, v);
-  end_values<N>(v, tr[0][2], tr[1][2]);
-  load_line<N, A>(G2, l, v);
-  end_values<N>(v, tr[0][3], tr[1][3]);
-}
-
 template <int N, typename Real, int GK>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, (Occupancy<N, Real>::value))
 sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__restrict__ dst)
 {
   using BK = Blocking<N>;
   constexpr int N2 = BK::N2, N3 = BK::N3, B = BK::B, NT = BK::NT, WSZ = BK::WSZ;
-  constexpr const auto &T = kTab<N>;
-  __shared__ Real smem[B * (N3 + WSZ)];
+  constexpr Tables<N> T = kTab<N>;
+  __shared__ Real smem[B * (2 * N3 + WSZ)];
 
   const int t = threadIdx.x;
   const bool act = t < NT;
@@ -420,69 +463,66 @@ sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__r
   const int cell = cell0 + cb;
   const bool valid = act && cell < op.ncells;
   const int nhere = min(B, op.ncells - cell0);
-  Real *Q = smem + cb * N3;
-  Real *W = smem + B * N3 + cb * WSZ;
-  Real *G0 = W, *G1 = W + N3, *G2 = W + 2 * N3;
+  Real *Q = smem + cb * N3;              // values at the Gauss points (kept to the end of the faces)
+  Real *R = smem + B * N3 + cb * N3;     // residual at the Gauss points
+  Real *W = smem + 2 * B * N3 + cb * WSZ;
+  Real *G0 = W, *G1 = W + N3;
   int ci[3];
   ci[0] = cell % op.ncell[0];
   ci[1] = (cell / op.ncell[0]) % op.ncell[1];
   ci[2] = cell / (op.ncell[0] * op.ncell[1]);
 
-  // (a) gather
+  // (a) gather the workgroup's cells (coalesced)
   const int64_t g0 = (int64_t)cell0 * N3;
   for (int i = t; i < B * N3; i += 256) smem[i] = (i < nhere * N3) ? src[g0 + i] : Real(0);
   __syncthreads();
 
-  // (b) basis change to the Gauss points, then the collocation derivative
+  // (b) basis change to the Gauss points (Eq. (6), right factor)
   if (act) sweep<N, 0, M_S>(Q, Q, l);
   __syncthreads();
   if (act) sweep<N, 1, M_S>(Q, Q, l);
   __syncthreads();
-  Real dz[N];
-  if (act) {
-    Real v[N], q[N];
-    load_line<N, 2>(Q, l, v);
-    eo_apply<N, M_S>(v, q);
-    store_line<N, 2>(Q, l, q);
-    eo_apply<N, M_DCO>(q, dz);
-    store_line<N, 2>(G2, l, dz);
-  }
+  if (act) sweep<N, 2, M_S>(Q, Q, l);
   __syncthreads();
+  // collocation derivative along x and y (z is taken in registers below)
   if (act) {
     sweep<N, 0, M_DCO>(Q, G0, l);
     sweep<N, 1, M_DCO>(Q, G1, l);
   }
   __syncthreads();
 
-  // (c) own-side traces of the six faces
-  Real tr[3][2][4];
+  // (c) cell quadrature-point operation along this thread's z-line; the
+  // stored geometry (J^{-T} and c det J w per point) is software-pipelined
+  // one point ahead so that at most two points' worth of it is in registers
   if (act) {
-    own_traces<N, Real, 0>(Q, G0, G1, G2, l, tr[0]);
-    own_traces<N, Real, 1>(Q, G0, G1, G2, l, tr[1]);
-    own_traces<N, Real, 2>(Q, G0, G1, G2, l, tr[2]);
-  }
-  __syncthreads();
-
-  // (d) cell quadrature-point operation along this thread's z-line
-  if (act) {
-    Real t2v[N];
+    Real qz[N], dz[N], t2v[N];
+    load_line<N, 2>(Q, l, qz);
+    eo_apply<N, M_DCO>(qz, dz);
+    Real gbuf[2][10];
+    auto load_geometry = [&](int k, Real (&gb)[10]) {
+      if constexpr (GK == CURVED) {
+        if (valid) {
+          const int64_t ix = (int64_t)cell * N3 + l + k * N2;
+          const int64_t cs = op.g.cell_stride;
+#pragma unroll
+          for (int m = 0; m < 10; ++m) gb[m] = op.g.cell[m * cs + ix];
+        } else {
+#pragma unroll
+          for (int m = 0; m < 10; ++m) gb[m] = Real(0);
+        }
+      }
+    };
+    load_geometry(0, gbuf[0]);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       const int p = l + k * N2;
       const Real g[3] = {G0[p], G1[p], dz[k]};
       Real o[3];
       if constexpr (GK == CURVED) {
-        Real jt[9], f = Real(0);
-        if (valid) {
-          const int64_t ix = (int64_t)cell * N3 + p;
-          const int64_t cs = op.g.cell_stride;
-#pragma unroll
-          for (int m = 0; m < 9; ++m) jt[m] = op.g.cell[m * cs + ix];
-          f = op.g.cell[9 * cs + ix];
-        } else {
-#pragma unroll
-          for (int m = 0; m < 9; ++m) jt[m] = Real(0);
-        }
+        const Real *jt = gbuf[k & 1];
+        const Real f = gbuf[k & 1][9];
+        if (k + 1 < N) load_geometry(k + 1, gbuf[(k + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
         Real gx[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) gx[a] = f * (jt[3 * a] * g[0] + jt[3 * a + 1] * g[1] + jt[3 * a + 2] * g[2]);
@@ -511,43 +551,45 @@ sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__r
     }
     Real rz[N];
     eo_apply<N, M_DCOT>(t2v, rz);
-    store_line<N, 2>(Q, l, rz);
+    store_line<N, 2>(R, l, rz);
   }
   __syncthreads();
+  // transposed collocation derivatives along x and y summed into R
   if (act) {
     Real v[N], r[N], q[N];
     load_line<N, 0>(G0, l, v);
     eo_apply<N, M_DCOT>(v, r);
-    load_line<N, 0>(Q, l, q);
+    load_line<N, 0>(R, l, q);
 #pragma unroll
     for (int m = 0; m < N; ++m) q[m] += r[m];
-    store_line<N, 0>(Q, l, q);
+    store_line<N, 0>(R, l, q);
   }
   __syncthreads();
   if (act) {
     Real v[N], r[N], q[N];
     load_line<N, 1>(G1, l, v);
     eo_apply<N, M_DCOT>(v, r);
-    load_line<N, 1>(Q, l, q);
+    load_line<N, 1>(R, l, q);
 #pragma unroll
     for (int m = 0; m < N; ++m) q[m] += r[m];
-    store_line<N, 1>(Q, l, q);
+    store_line<N, 1>(R, l, q);
   }
   __syncthreads();
 
-  // (e) face terms, direction by direction
-  face_direction<N, Real, GK, 0>(op, src, Q, W, l, cell, ci, act, valid, tr[0]);
-  face_direction<N, Real, GK, 1>(op, src, Q, W, l, cell, ci, act, valid, tr[1]);
-  face_direction<N, Real, GK, 2>(op, src, Q, W, l, cell, ci, act, valid, tr[2]);
+  // (d) face terms, direction by direction (W is free again)
+  face_direction<N, Real, GK, 0>(op, src, Q, R, W, l, cell, ci, act, valid);
+  face_direction<N, Real, GK, 1>(op, src, Q, R, W, l, cell, ci, act, valid);
+  face_direction<N, Real, GK, 2>(op, src, Q, R, W, l, cell, ci, act, valid);
 
-  // (f) back to the Gauss-Lobatto basis and write
-  if (act) sweep<N, 0, M_ST>(Q, Q, l);
+  // (e) back to the Gauss-Lobatto basis (transposed basis change) and write
+  if (act) sweep<N, 0, M_ST>(R, R, l);
   __syncthreads();
-  if (act) sweep<N, 1, M_ST>(Q, Q, l);
+  if (act) sweep<N, 1, M_ST>(R, R, l);
   __syncthreads();
-  if (act) sweep<N, 2, M_ST>(Q, Q, l);
+  if (act) sweep<N, 2, M_ST>(R, R, l);
   __syncthreads();
-  for (int i = t; i < nhere * N3; i += 256) dst[g0 + i] = smem[i];
+  const Real *Rall = smem + B * N3;
+  for (int i = t; i < nhere * N3; i += 256) dst[g0 + i] = Rall[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -564,7 +606,7 @@ __global__ void __launch_bounds__(1024)
 sipg_diag_kernel(const OpView<double> op, double *__restrict__ d64, float *__restrict__ d32)
 {
   constexpr int N2 = N * N, N3 = N2 * N;
-  constexpr const auto &T = kTab<N>;
+  constexpr Tables<N> T = kTab<N>;
   constexpr int NG = (GK == CURVED) ? 10 : 1;
   __shared__ double geo[NG * N3];
   const int cell = blockIdx.x;
