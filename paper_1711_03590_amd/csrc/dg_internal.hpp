@@ -7,7 +7,7 @@
 #include <cstdint>
 #include <string>
 
-#include "../../include/dg.h"
+#include "dg.h"
 
 namespace dgk {
 

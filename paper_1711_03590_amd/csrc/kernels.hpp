@@ -3,7 +3,7 @@
 // representation.  One translation unit per N instantiates them.
 //
 // Operator: y = A u (Sec. 2, Eq. (3)) for the SIPG form of Sec. 2, Eq. (2),
-// evaluated cell by cell.  Each workgroup owns B = 256 / N^2 cells and maps
+// evaluated cell by cell.  Each workgroup owns B = TPB / N^2 cells and maps
 // one thread to one 1D line of each cell (N^2 lines per sweep direction).
 // Per cell, in one pass (Algorithm 1 steps (ii)-(iv) fused, Design Choice 2):
 //   (a) gather the cell's N^3 coefficients into LDS (coalesced block copy);
@@ -178,10 +178,15 @@ __device__ __forceinline__ int xcd_remap(int b, int G)
   return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + k;
 }
 
+#ifndef DG_WG_WAVES
+#define DG_WG_WAVES 2
+#endif
 template <int N>
 struct Blocking {
   static constexpr int N2 = N * N, N3 = N2 * N;
-  static constexpr int B = 256 / N2;         // cells per workgroup
+  static constexpr int TPB0 = 64 * DG_WG_WAVES;
+  static constexpr int TPB = TPB0 >= N2 ? TPB0 : ((N2 + 63) / 64) * 64;  // threads per workgroup
+  static constexpr int B = TPB / N2;         // cells per workgroup
   static constexpr int NT = B * N2;          // active threads
   static constexpr int WSZ = (2 * N3 > 10 * N2) ? 2 * N3 : 10 * N2;  // gradient / face scratch per cell
 };
@@ -200,8 +205,9 @@ template <int N, typename Real>
 struct Occupancy {
   static constexpr int lds = Blocking<N>::B * (2 * Blocking<N>::N3 + Blocking<N>::WSZ) * (int)sizeof(Real);
   static constexpr int wgs = 163840 / lds;
+  static constexpr int waves = wgs * (Blocking<N>::TPB / 64) / 4;
   static constexpr int cap = sizeof(Real) == 8 ? DG_MAX_WAVES_F64 : DG_MAX_WAVES_F32;
-  static constexpr int value = wgs < 1 ? 1 : (wgs > cap ? cap : wgs);
+  static constexpr int value = waves < 1 ? 1 : (waves > cap ? cap : waves);
 };
 
 // face index of the face of cell ci on side s of direction A
@@ -266,6 +272,28 @@ __device__ __forceinline__ void end_derivatives(const Real (&v)[N], Real &lo, Re
   hi = so - se;
 }
 
+// The two neighbours' normal lines through face point l for direction A
+// (zeros where there is no neighbour); issued ahead of their use so that the
+// loads overlap the preceding phase.
+template <int N, typename Real, int A>
+__device__ __forceinline__ void load_neighbour_lines(const OpView<Real> &op, const Real *__restrict__ src,
+                                                     int cell, int l, const int (&ci)[3], bool valid,
+                                                     Real (&nb)[2][N])
+{
+  constexpr int N3 = N * N * N;
+  const int64_t cstride = (A == 0) ? 1 : (A == 1 ? (int64_t)op.ncell[0] : (int64_t)op.ncell[0] * op.ncell[1]);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int cn = ci[A] + (s ? 1 : -1);
+    if (valid && cn >= 0 && cn < op.ncell[A]) {
+      load_line<N, A>(src + (int64_t)(cell + (s ? cstride : -cstride)) * N3, l, nb[s]);
+    } else {
+#pragma unroll
+      for (int m = 0; m < N; ++m) nb[s][m] = Real(0);
+    }
+  }
+}
+
 // Face terms of direction A for this thread group's cell: the face integrals
 // of Sec. 2 Eq. (2) over the cell's two faces normal to A, own side only
 // (the element's share of Algorithm 1 steps (iii)-(iv)), added into the
@@ -277,7 +305,7 @@ __device__ __forceinline__ void end_derivatives(const Real (&v)[N], Real &lo, Re
 template <int N, typename Real, int GK, int A>
 __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Real *__restrict__ src,
                                                const Real *Q, Real *R, Real *W, int l, int cell,
-                                               const int (&ci)[3], bool act, bool valid)
+                                               const int (&ci)[3], bool act, bool valid, Real (&nb)[2][N])
 {
   constexpr int N2 = N * N, N3 = N2 * N;
   constexpr int t1 = (A == 0) ? 1 : 0, t2 = (A == 2) ? 1 : 2;
@@ -288,8 +316,7 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
   Real *V = W + 8 * N2;   // [s] u- + u+
   Real *dV = W + 4 * N2;  // [s][d_t1 V, d_t2 V]
   Real *Z = W;            // [s][tg_t1, tg_t2]
-  Real *Z2 = W + 4 * N2;  // [s][Dco^T along t1 of tg_t1 + ..., Dco^T along t2 of tg_t2]
-  const int64_t cstride = (A == 0) ? 1 : (A == 1 ? (int64_t)op.ncell[0] : (int64_t)op.ncell[0] * op.ncell[1]);
+  Real *Z2 = W + 4 * N2;  // [s][Dco^T along t1 of tg_t1, Dco^T along t2 of tg_t2]
   bool interior[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
@@ -299,36 +326,36 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
   // S1: own value and reference normal derivative at this face point (the
   // Gauss-point data is tangentially at the face's Gauss points already);
   // the neighbour's value and normal derivative at the Gauss-Lobatto nodes of
-  // the shared face: end node (nodal basis) and D_f of Eq. (7)
+  // the shared face from its prefetched normal line: end node (nodal basis)
+  // and D_f of Eq. (7).  The face geometry used in S6 is requested here.
   Real um[2], dm[2];
+  Real jg[2][3] = {{Real(0), Real(0), Real(0)}, {Real(0), Real(0), Real(0)}}, cds[2] = {Real(0), Real(0)};
   if (act) {
+    if (valid) {
+      face_geometry<N, Real, GK, A>(op, ci, 0, l, jg[0], cds[0]);
+      face_geometry<N, Real, GK, A>(op, ci, 1, l, jg[1], cds[1]);
+    }
     Real v[N];
     load_line<N, A>(Q, l, v);
     end_values<N>(v, um[0], um[1]);
     end_derivatives<N>(v, dm[0], dm[1]);
+    // neighbour below: the shared face is its xi_A = 1 side; above: xi_A = 0
+    Real der0 = Real(-0.0), der1 = Real(-0.0);
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      Real val = Real(0), der = Real(0);
-      if (interior[s]) {
-        const Real *nb = src + (int64_t)(cell + (s ? cstride : -cstride)) * N3;
-        Real w[N];
-        load_line<N, A>(nb, l, w);
-        der = Real(-0.0);
-        if (s == 0) {  // neighbour below: the shared face is its xi_A = 1 side
-          val = w[N - 1];
-#pragma unroll
-          for (int m = 0; m < N; ++m) der = madd(T.F1[m], w[m], der);
-        } else {       // neighbour above: its xi_A = 0 side
-          val = w[0];
-#pragma unroll
-          for (int m = 0; m < N; ++m) der = madd(T.F0[m], w[m], der);
-        }
-      }
-      X[(2 * s) * N2 + l] = val;
-      X[(2 * s + 1) * N2 + l] = der;
+    for (int m = 0; m < N; ++m) {
+      der0 = madd(T.F1[m], nb[0][m], der0);
+      der1 = madd(T.F0[m], nb[1][m], der1);
     }
+    X[0 * N2 + l] = nb[0][N - 1];
+    X[1 * N2 + l] = der0;
+    X[2 * N2 + l] = nb[1][0];
+    X[3 * N2 + l] = der1;
   }
   __syncthreads();
+  // the next direction's neighbour lines, consumed by its S1
+  if constexpr (A < 2) {
+    if (act) load_neighbour_lines<N, Real, A + 1>(op, src, cell, l, ci, valid, nb);
+  }
   // S2: neighbour traces, basis change along t1 (one line per job)
   // (2N jobs; with N^2 < 2N threads per cell a thread takes several)
   if (act) for (int jb = l; jb < 2 * N; jb += N2) {
@@ -394,18 +421,16 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
   if (act) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      Real j[3] = {Real(0), Real(0), Real(0)}, cds = Real(0);
-      if (valid) face_geometry<N, Real, GK, A>(op, ci, s, l, j, cds);
-      if (!interior[s] && op.bc[2 * A + s] != 0) cds = Real(0);  // homogeneous Neumann
+      const Real c_ds = (!interior[s] && op.bc[2 * A + s] != 0) ? Real(0) : cds[s];  // Neumann: nothing
       const Real sg = s ? Real(1) : Real(-1);
-      const Real je[3] = {sg * j[0], sg * j[1], sg * j[2]};
+      const Real je[3] = {sg * jg[s][0], sg * jg[s][1], sg * jg[s][2]};
       Real g[3];
       g[t1] = dV[(2 * s) * N2 + l];
       g[t2] = dV[(2 * s + 1) * N2 + l];
       g[A] = dsum[s];
       const Real avg = Real(0.5) * (je[0] * g[0] + je[1] * g[1] + je[2] * g[2]);
-      tv[s] = cds * (op.tau[A] * jump[s] - avg);
-      const Real gfac = Real(-0.5) * cds * jump[s];
+      tv[s] = c_ds * (op.tau[A] * jump[s] - avg);
+      const Real gfac = Real(-0.5) * c_ds * jump[s];
       tga[s] = gfac * je[A];
       Z[(2 * s) * N2 + l] = gfac * je[t1];
       Z[(2 * s + 1) * N2 + l] = gfac * je[t2];
@@ -446,11 +471,11 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
 }
 
 template <int N, typename Real, int GK>
-__global__ void __launch_bounds__(256, (Occupancy<N, Real>::value))
+__global__ void __launch_bounds__(Blocking<N>::TPB, (Occupancy<N, Real>::value))
 sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__restrict__ dst)
 {
   using BK = Blocking<N>;
-  constexpr int N2 = BK::N2, N3 = BK::N3, B = BK::B, NT = BK::NT, WSZ = BK::WSZ;
+  constexpr int N2 = BK::N2, N3 = BK::N3, B = BK::B, NT = BK::NT, WSZ = BK::WSZ, TPB = BK::TPB;
   constexpr Tables<N> T = kTab<N>;
   __shared__ Real smem[B * (2 * N3 + WSZ)];
 
@@ -474,7 +499,7 @@ sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__r
 
   // (a) gather the workgroup's cells (coalesced)
   const int64_t g0 = (int64_t)cell0 * N3;
-  for (int i = t; i < B * N3; i += 256) smem[i] = (i < nhere * N3) ? src[g0 + i] : Real(0);
+  for (int i = t; i < B * N3; i += TPB) smem[i] = (i < nhere * N3) ? src[g0 + i] : Real(0);
   __syncthreads();
 
   // (b) basis change to the Gauss points (Eq. (6), right factor)
@@ -554,7 +579,10 @@ sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__r
     store_line<N, 2>(R, l, rz);
   }
   __syncthreads();
-  // transposed collocation derivatives along x and y summed into R
+  // transposed collocation derivatives along x and y summed into R; the
+  // x-direction neighbour lines for the face phase are requested first
+  Real nb[2][N];
+  if (act) load_neighbour_lines<N, Real, 0>(op, src, cell, l, ci, valid, nb);
   if (act) {
     Real v[N], r[N], q[N];
     load_line<N, 0>(G0, l, v);
@@ -577,9 +605,9 @@ sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__r
   __syncthreads();
 
   // (d) face terms, direction by direction (W is free again)
-  face_direction<N, Real, GK, 0>(op, src, Q, R, W, l, cell, ci, act, valid);
-  face_direction<N, Real, GK, 1>(op, src, Q, R, W, l, cell, ci, act, valid);
-  face_direction<N, Real, GK, 2>(op, src, Q, R, W, l, cell, ci, act, valid);
+  face_direction<N, Real, GK, 0>(op, src, Q, R, W, l, cell, ci, act, valid, nb);
+  face_direction<N, Real, GK, 1>(op, src, Q, R, W, l, cell, ci, act, valid, nb);
+  face_direction<N, Real, GK, 2>(op, src, Q, R, W, l, cell, ci, act, valid, nb);
 
   // (e) back to the Gauss-Lobatto basis (transposed basis change) and write
   if (act) sweep<N, 0, M_ST>(R, R, l);
@@ -589,7 +617,7 @@ sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__r
   if (act) sweep<N, 2, M_ST>(R, R, l);
   __syncthreads();
   const Real *Rall = smem + B * N3;
-  for (int i = t; i < nhere * N3; i += 256) dst[g0 + i] = Rall[i];
+  for (int i = t; i < nhere * N3; i += TPB) dst[g0 + i] = Rall[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -719,17 +747,17 @@ hipError_t launch_apply(const dg_op *op, const void *src, void *dst, bool f32, h
     const float *x = static_cast<const float *>(src);
     float *y = static_cast<float *>(dst);
     switch (op->gk) {
-      case CURVED: hipLaunchKernelGGL((sipg_apply_kernel<N, float, CURVED>), dim3(grid), dim3(256), 0, s, op->v32, x, y); break;
-      case AFFINE_VAR: hipLaunchKernelGGL((sipg_apply_kernel<N, float, AFFINE_VAR>), dim3(grid), dim3(256), 0, s, op->v32, x, y); break;
-      default: hipLaunchKernelGGL((sipg_apply_kernel<N, float, AFFINE_CONST>), dim3(grid), dim3(256), 0, s, op->v32, x, y); break;
+      case CURVED: hipLaunchKernelGGL((sipg_apply_kernel<N, float, CURVED>), dim3(grid), dim3(BK::TPB), 0, s, op->v32, x, y); break;
+      case AFFINE_VAR: hipLaunchKernelGGL((sipg_apply_kernel<N, float, AFFINE_VAR>), dim3(grid), dim3(BK::TPB), 0, s, op->v32, x, y); break;
+      default: hipLaunchKernelGGL((sipg_apply_kernel<N, float, AFFINE_CONST>), dim3(grid), dim3(BK::TPB), 0, s, op->v32, x, y); break;
     }
   } else {
     const double *x = static_cast<const double *>(src);
     double *y = static_cast<double *>(dst);
     switch (op->gk) {
-      case CURVED: hipLaunchKernelGGL((sipg_apply_kernel<N, double, CURVED>), dim3(grid), dim3(256), 0, s, op->v64, x, y); break;
-      case AFFINE_VAR: hipLaunchKernelGGL((sipg_apply_kernel<N, double, AFFINE_VAR>), dim3(grid), dim3(256), 0, s, op->v64, x, y); break;
-      default: hipLaunchKernelGGL((sipg_apply_kernel<N, double, AFFINE_CONST>), dim3(grid), dim3(256), 0, s, op->v64, x, y); break;
+      case CURVED: hipLaunchKernelGGL((sipg_apply_kernel<N, double, CURVED>), dim3(grid), dim3(BK::TPB), 0, s, op->v64, x, y); break;
+      case AFFINE_VAR: hipLaunchKernelGGL((sipg_apply_kernel<N, double, AFFINE_VAR>), dim3(grid), dim3(BK::TPB), 0, s, op->v64, x, y); break;
+      default: hipLaunchKernelGGL((sipg_apply_kernel<N, double, AFFINE_CONST>), dim3(grid), dim3(BK::TPB), 0, s, op->v64, x, y); break;
     }
   }
   return hipGetLastError();
