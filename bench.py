@@ -198,13 +198,13 @@ def bench_solve(dg, torch, np, synth, reps):
     op = dg.Operator(32, 5, curved=True, variable_coef=True)
     b = op.rhs()
     out = {}
-    for mode in ("mixed", "fp64"):
+    for name, mode in (("mixed", 2), ("mixed_ir_restarted", 1), ("fp64", 0)):
         times, last = [], None
         for r in range(reps + 1):
             x = torch.zeros_like(b)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            x, st = op.cg_solve(b, x, mixed=(mode == "mixed"), rel_tol=1e-10)
+            x, st = op.cg_solve(b, x, mode=mode, rel_tol=1e-10)
             torch.cuda.synchronize()
             el = (time.perf_counter() - t0) * 1e3
             if r > 0:
@@ -213,7 +213,7 @@ def bench_solve(dg, torch, np, synth, reps):
         x, st = last
         l2, h1 = op.error_manufactured(x)
         t = np.array(times)
-        out[mode] = {"p50_ms": float(np.percentile(t, 50)), "p99_ms": float(np.percentile(t, 99)),
+        out[name] = {"p50_ms": float(np.percentile(t, 50)), "p99_ms": float(np.percentile(t, 99)), "mode": mode,
                      "reps": reps, "converged": st["converged"], "iters_inner": st["iters_inner"],
                      "iters_outer": st["iters_outer"], "applies_f64": st["applies_f64"],
                      "applies_f32": st["applies_f32"], "final_rel_residual": st["final_rel_residual"],

@@ -146,7 +146,13 @@ dg_status dg_error_manufactured(dg_op *op, dg_vec x, void *stream, double err[2]
  *   mode 0: FP64 CG throughout.
  *   mode 1: FP32 CG (FP32 applies, FP32 accumulation) on the correction
  *           equation inside FP64 iterative refinement: r = b - A x in FP64,
- *           d ~ A^{-1} r in FP32 to rel_tol_inner, x += d in FP64.
+ *           d ~ A^{-1} r in FP32 to rel_tol_inner, x += d in FP64; every
+ *           refinement step restarts the FP32 CG.
+ *   mode 2: the same split of precisions with reliable updates: one FP32 CG
+ *           recurrence whose residual is replaced by the FP64 residual b - A x
+ *           (and whose correction is flushed into the FP64 x) each time it has
+ *           dropped by the factor rel_tol_inner (e.g. 0.1) since the last
+ *           replacement; the search direction is kept across replacements.
  * Stops when ||b - A x||_2 <= rel_tol * ||b||_2 (always checked with an FP64
  * apply).  x holds the initial guess on entry.  Synchronises the stream.
  * Returns DG_ERR_NOT_CONVERGED (stats filled) when the limits are hit. */
@@ -154,14 +160,14 @@ typedef struct {
   int mode;
   double rel_tol;
   double rel_tol_inner;
-  int max_iter;        /* FP64 mode: CG iterations; mixed: inner iterations per refinement step */
-  int max_outer;       /* mixed mode: refinement steps */
+  int max_iter;        /* modes 0, 2: CG iterations; mode 1: inner iterations per refinement step */
+  int max_outer;       /* mode 1: refinement steps (must be >= 1 in modes 1, 2) */
   int check_every;     /* read the residual norm back every this many iterations (>= 1) */
 } dg_solve_params;
 
 typedef struct {
   int iters_inner;         /* total CG iterations (both modes) */
-  int iters_outer;         /* refinement steps (mixed mode), 0 in FP64 mode */
+  int iters_outer;         /* refinement steps (modes 1, 2), 0 in FP64 mode */
   int applies_f64;
   int applies_f32;
   double final_rel_residual;

@@ -252,18 +252,26 @@ class Operator:
         check(lib().dg_error_manufactured(self._h, vec(x), _stream(stream), err))
         return err[0], err[1]
 
-    def cg_solve(self, b, x=None, *, mixed=True, rel_tol=1e-10, rel_tol_inner=1e-4, max_iter=20000,
+    def cg_solve(self, b, x=None, *, mixed=True, mode=None, rel_tol=1e-10, rel_tol_inner=None, max_iter=20000,
                  max_outer=50, check_every=10, stream=None):
+        """Jacobi-PCG for A x = b (FP64 vectors).  mode 0: FP64 CG; 1: FP32 CG
+        inside FP64 iterative refinement (default when mixed); 2: the same with
+        reliable updates.  Returns (x, stats dict with 'converged')."""
         torch = _torch()
+        if mode is None:
+            mode = 1 if mixed else 0
+        if rel_tol_inner is None:
+            rel_tol_inner = 0.1 if mode == 2 else 1e-4
         if x is None:
             x = torch.zeros_like(b)
-        p = SolveParams(1 if mixed else 0, rel_tol, rel_tol_inner, max_iter, max_outer, check_every)
+        p = SolveParams(mode, rel_tol, rel_tol_inner, max_iter, max_outer, check_every)
         st = SolveStats()
         rc = lib().dg_cg_solve(self._h, vec(b), vec(x), ctypes.byref(p), ctypes.byref(st), _stream(stream))
         if rc not in (DG_OK, DG_ERR_NOT_CONVERGED):
             check(rc)
         out = st.as_dict()
         out["converged"] = rc == DG_OK
+        out["mode"] = mode
         return x, out
 
     def close(self):

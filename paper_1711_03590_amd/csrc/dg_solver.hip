@@ -1,10 +1,360 @@
-// dg_solver.hip -- Jacobi-preconditioned CG (FP64) and FP32 CG inside FP64
-// iterative refinement.
+// dg_solver.hip -- Jacobi-preconditioned conjugate gradients on the matrix-
+// free SIPG operator: FP64 CG, and FP32 CG (FP32 applies, FP32 accumulation)
+// on the correction equation inside FP64 iterative refinement.
+//
+// Every reduction is deterministic: dot products are summed over a fixed
+// partition of the vector (kRedBlocks blocks, grid-stride), each block in a
+// fixed tree order, and the block partials are reduced in a fixed order by
+// every block that needs the result.  Scalars (alpha, beta) never leave the
+// device; the host reads the residual norm back only every check_every
+// iterations, asynchronously into pinned memory.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
 #include "dg_internal.hpp"
+#include "solver_kernels.hpp"
+
+namespace dgk {
+
+namespace {
+
+struct Pinned {
+  double *p = nullptr;
+  Pinned() { (void)hipHostMalloc(reinterpret_cast<void **>(&p), 8 * sizeof(double), hipHostMallocDefault); }
+  ~Pinned()
+  {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+// device workspace of one solve, released through the op's allocator
+struct Workspace {
+  dg_op *op;
+  std::vector<void *> ptr;
+  explicit Workspace(dg_op *o) : op(o) {}
+  void *get(size_t bytes)
+  {
+    void *p = op_alloc(op, bytes);
+    if (p) ptr.push_back(p);
+    return p;
+  }
+  ~Workspace()
+  {
+    for (void *p : ptr) op_free(op, p);
+  }
+};
+
+// the vectors of one PCG run in precision Real
+template <typename Real, typename Acc>
+struct PcgBuffers {
+  Real *r = nullptr, *p = nullptr, *q = nullptr;
+  Acc *part = nullptr;
+  bool alloc(Workspace &ws, int64_t n)
+  {
+    r = static_cast<Real *>(ws.get(n * sizeof(Real)));
+    p = static_cast<Real *>(ws.get(n * sizeof(Real)));
+    q = static_cast<Real *>(ws.get(n * sizeof(Real)));
+    part = static_cast<Acc *>(ws.get(3 * kRedBlocks * sizeof(Acc) + 4 * sizeof(Acc)));
+    return r && p && q && part;
+  }
+};
+
+template <typename Acc>
+hipError_t norm2(const void *x, bool f32, int64_t n, Acc *part, Acc *out, hipStream_t s)
+{
+  if (f32) {
+    const float *v = static_cast<const float *>(x);
+    hipLaunchKernelGGL((dot_partial_kernel<float, Acc>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, v, v, n, part);
+  } else {
+    const double *v = static_cast<const double *>(x);
+    hipLaunchKernelGGL((dot_partial_kernel<double, Acc>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, v, v, n, part);
+  }
+  hipLaunchKernelGGL((finalize_kernel<Acc>), dim3(1), dim3(kRedThreads), 0, s, part, kRedBlocks, out);
+  return hipGetLastError();
+}
+
+// Preconditioned CG on A x = rhs in precision Real (accumulation Acc), x and
+// rhs device vectors; x holds the initial guess.  Stops when the recurrence
+// residual satisfies ||r|| <= tol_abs, or after max_iter iterations.
+// Workspace: r, p, q (Real), partials.  Returns iterations done in *iters.
+template <typename Real, typename Acc>
+dg_status pcg(dg_op *op, const Real *rhs, Real *x, bool x_zero, double tol_abs, int max_iter, int check_every,
+              const PcgBuffers<Real, Acc> &buf, Pinned &pin, hipStream_t s, int *iters, double *rnorm)
+{
+  const int64_t n = op->ndofs;
+  const bool f32 = sizeof(Real) == 4;
+  Real *r = buf.r, *p = buf.p, *q = buf.q;
+  Acc *part = buf.part;
+  Acc *pq_part = part;                    // kRedBlocks
+  Acc *rz_part = part + kRedBlocks;       // 2 * kRedBlocks: r.z and r.r interleaved
+  Acc *scal = part + 3 * kRedBlocks;      // rz[2] (ping-pong), rr, spare
+  const Real *d = static_cast<const Real *>(op->diag[f32 ? 1 : 0]);
+  const int grid = kRedBlocks;
+  // r = rhs - A x
+  if (x_zero) {
+    hipLaunchKernelGGL((copy_kernel<Real>), dim3(grid), dim3(kRedThreads), 0, s, rhs, r, n);
+  } else {
+    DG_HIP(launch_apply_any(op, x, q, f32, s));
+    hipLaunchKernelGGL((sub_kernel<Real>), dim3(grid), dim3(kRedThreads), 0, s, rhs, q, r, n);
+  }
+  // z = r / d, p = z, rz = r.z, rr = r.r
+  hipLaunchKernelGGL((rz_partial_kernel<Real, Acc>), dim3(grid), dim3(kRedThreads), 0, s, r, d, n, rz_part);
+  hipLaunchKernelGGL((cg_pupdate_kernel<Real, Acc>), dim3(grid), dim3(kRedThreads), 0, s, p, r, d, n, rz_part,
+                     scal, 0, 0);
+  DG_HIP(hipGetLastError());
+  int par = 1;  // scal[par] holds the current r.z
+  int it = 0;
+  bool done = false;
+  auto read_rr = [&](double *out) -> dg_status {
+    DG_HIP(hipMemcpyAsync(pin.p, scal + 2, sizeof(Acc), hipMemcpyDeviceToHost, s));
+    DG_HIP(hipStreamSynchronize(s));
+    *out = std::sqrt((double)*reinterpret_cast<Acc *>(pin.p));
+    return DG_OK;
+  };
+  double rn = 0.0;
+  dg_status st = read_rr(&rn);
+  if (st != DG_OK) return st;
+  if (!(rn > tol_abs)) done = true;
+  while (!done && it < max_iter) {
+    DG_HIP(launch_apply_any(op, p, q, f32, s));
+    hipLaunchKernelGGL((dot_partial_kernel<Real, Acc>), dim3(grid), dim3(kRedThreads), 0, s, p, q, n, pq_part);
+    hipLaunchKernelGGL((cg_update_kernel<Real, Acc>), dim3(grid), dim3(kRedThreads), 0, s, x, r, p, q, d, n,
+                       pq_part, scal, par, rz_part);
+    hipLaunchKernelGGL((cg_pupdate_kernel<Real, Acc>), dim3(grid), dim3(kRedThreads), 0, s, p, r, d, n, rz_part,
+                       scal, 1, par);
+    DG_HIP(hipGetLastError());
+    par = 1 - par;
+    ++it;
+    if (it % check_every == 0 || it == max_iter) {
+      if ((st = read_rr(&rn)) != DG_OK) return st;
+      if (!(rn > tol_abs)) done = true;
+      if (!std::isfinite(rn)) return fail(DG_ERR_NOT_CONVERGED, "CG breakdown (non-finite residual)");
+    }
+  }
+  *iters = it;
+  *rnorm = rn;
+  return done ? DG_OK : DG_ERR_NOT_CONVERGED;
+}
+
+// FP32 Jacobi-PCG with reliable updates inside FP64 refinement: the FP32
+// recurrence runs on the relative system A e = r / ||b||; each time its
+// residual has dropped tenfold since the last refinement (checked every
+// check_every iterations), the FP32 correction is flushed into the FP64
+// solution (x += ||b|| e), the FP64 residual b - A x is recomputed with an
+// FP64 apply and replaces the FP32 residual, and the search direction is
+// kept, so no Krylov information is lost at a refinement step.
+dg_status pcg_reliable(dg_op *op, const double *b, double *x, double nb, double tol, double delta, int max_iter,
+                       int check_every, const PcgBuffers<float, float> &buf, float *e, double *r64, double *dpart,
+                       Pinned &pin, hipStream_t s, dg_solve_stats &st, double *rel_out)
+{
+  const int64_t n = op->ndofs;
+  const int grid = kRedBlocks;
+  float *r = buf.r, *p = buf.p, *q = buf.q;
+  float *pq_part = buf.part, *rz_part = buf.part + kRedBlocks, *scal = buf.part + 3 * kRedBlocks;
+  double *dscal = dpart + kRedBlocks;
+  const float *d = static_cast<const float *>(op->diag[1]);
+  auto read = [&](const void *dev, size_t bytes, void *host) -> dg_status {
+    DG_HIP(hipMemcpyAsync(pin.p, dev, bytes, hipMemcpyDeviceToHost, s));
+    DG_HIP(hipStreamSynchronize(s));
+    memcpy(host, pin.p, bytes);
+    return DG_OK;
+  };
+  // FP64 residual r64 = b - A x, its relative norm, and r = r64 / ||b|| in FP32
+  auto refresh = [&](double *rel) -> dg_status {
+    DG_HIP(launch_apply_any(op, x, r64, false, s));
+    hipLaunchKernelGGL((sub_kernel<double>), dim3(grid), dim3(kRedThreads), 0, s, b, r64, r64, n);
+    hipLaunchKernelGGL((dot_partial_kernel<double, double>), dim3(grid), dim3(kRedThreads), 0, s, r64, r64, n, dpart);
+    hipLaunchKernelGGL((finalize_kernel<double>), dim3(1), dim3(kRedThreads), 0, s, dpart, kRedBlocks, dscal);
+    hipLaunchKernelGGL(scale_to_f32_kernel, dim3(grid), dim3(kRedThreads), 0, s, r64, 1.0 / nb, r, n);
+    DG_HIP(hipGetLastError());
+    double v;
+    dg_status e2 = read(dscal, sizeof(double), &v);
+    if (e2 != DG_OK) return e2;
+    *rel = std::sqrt(v) / nb;
+    st.applies_f64 += 1;
+    return DG_OK;
+  };
+  double rel;
+  dg_status rc = refresh(&rel);
+  if (rc != DG_OK) return rc;
+  *rel_out = rel;
+  if (rel <= tol) return DG_OK;
+  hipLaunchKernelGGL((fill_kernel<float>), dim3(grid), dim3(kRedThreads), 0, s, e, 0.0f, n);
+  hipLaunchKernelGGL((rz_partial_kernel<float, float>), dim3(grid), dim3(kRedThreads), 0, s, r, d, n, rz_part);
+  hipLaunchKernelGGL((cg_pupdate_kernel<float, float>), dim3(grid), dim3(kRedThreads), 0, s, p, r, d, n, rz_part,
+                     scal, 0, 0);
+  DG_HIP(hipGetLastError());
+  int par = 1;
+  double rlast = rel;
+  st.iters_outer = 1;
+  for (int it = 1; it <= max_iter; ++it) {
+    DG_HIP(launch_apply_any(op, p, q, true, s));
+    hipLaunchKernelGGL((dot_partial_kernel<float, float>), dim3(grid), dim3(kRedThreads), 0, s, p, q, n, pq_part);
+    hipLaunchKernelGGL((cg_update_kernel<float, float>), dim3(grid), dim3(kRedThreads), 0, s, e, r, p, q, d, n,
+                       pq_part, scal, par, rz_part);
+    hipLaunchKernelGGL((cg_pupdate_kernel<float, float>), dim3(grid), dim3(kRedThreads), 0, s, p, r, d, n, rz_part,
+                       scal, 1, par);
+    DG_HIP(hipGetLastError());
+    par = 1 - par;
+    st.iters_inner += 1;
+    st.applies_f32 += 1;
+    if (it % check_every != 0 && it != max_iter) continue;
+    float rr;
+    if ((rc = read(scal + 2, sizeof(float), &rr)) != DG_OK) return rc;
+    const double r32 = std::sqrt((double)rr);
+    if (!std::isfinite(r32)) return fail(DG_ERR_NOT_CONVERGED, "CG breakdown (non-finite residual)");
+    if (r32 <= tol || r32 < delta * rlast || it == max_iter) {
+      // refinement step: flush the correction, replace the residual
+      hipLaunchKernelGGL(axpy_f32_kernel, dim3(grid), dim3(kRedThreads), 0, s, x, nb, e, n);
+      hipLaunchKernelGGL((fill_kernel<float>), dim3(grid), dim3(kRedThreads), 0, s, e, 0.0f, n);
+      DG_HIP(hipGetLastError());
+      if ((rc = refresh(&rel)) != DG_OK) return rc;
+      *rel_out = rel;
+      if (rel <= tol) return DG_OK;
+      st.iters_outer += 1;
+      rlast = rel;
+      // r.z of the replaced residual becomes the current r.z
+      hipLaunchKernelGGL((rz_partial_kernel<float, float>), dim3(grid), dim3(kRedThreads), 0, s, r, d, n, rz_part);
+      hipLaunchKernelGGL((rz_finalize_kernel<float>), dim3(1), dim3(kRedThreads), 0, s, rz_part, scal, par);
+      DG_HIP(hipGetLastError());
+    }
+  }
+  return DG_ERR_NOT_CONVERGED;
+}
+
+}  // namespace
+
+}  // namespace dgk
 
 using namespace dgk;
 
-extern "C" dg_status dg_cg_solve(dg_op *, dg_vec, dg_vec, const dg_solve_params *, dg_solve_stats *, void *)
+extern "C" dg_status dg_cg_solve(dg_op *op, dg_vec b, dg_vec x, const dg_solve_params *prm, dg_solve_stats *stats,
+                                 void *stream)
 {
-  return fail(DG_ERR_UNSUPPORTED, "dg_cg_solve: not built yet");
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!op || !prm) return fail(DG_ERR_ARG, "null argument");
+  if (!b.data || !x.data || b.n != op->ndofs || x.n != op->ndofs || b.dtype != DG_F64 || x.dtype != DG_F64)
+    return fail(DG_ERR_ARG, "b and x must be FP64 vectors of length dg_n_dofs");
+  if (b.data == x.data) return fail(DG_ERR_ARG, "b and x alias");
+  if (prm->mode < 0 || prm->mode > 2) return fail(DG_ERR_ARG, "mode must be 0 (FP64), 1 (mixed) or 2 (mixed, reliable updates)");
+  if (!(prm->rel_tol > 0) || prm->max_iter < 1 || prm->check_every < 1) return fail(DG_ERR_ARG, "bad solver limits");
+  if (!(op->precisions & DG_PREC_F64)) return fail(DG_ERR_ARG, "the op needs FP64 data");
+  if (prm->mode >= 1 && (!(op->precisions & DG_PREC_F32) || !(prm->rel_tol_inner > 0) || prm->max_outer < 1))
+    return fail(DG_ERR_ARG, "mixed mode needs FP32 data, rel_tol_inner > 0 and max_outer >= 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  dg_solve_stats st{};
+  const int64_t n = op->ndofs;
+  const int grid = kRedBlocks;
+  Pinned pin;
+  if (!pin.p) return fail(DG_ERR_HIP, "pinned host allocation failed");
+  Workspace ws(op);
+  double *part = static_cast<double *>(ws.get((kRedBlocks + 8) * sizeof(double)));
+  double *r64 = static_cast<double *>(ws.get(n * sizeof(double)));
+  if (!part || !r64) return fail(DG_ERR_OOM, "solver workspace allocation failed");
+  double *dscal = part + kRedBlocks;
+  double *xp = static_cast<double *>(x.data);
+  const double *bp = static_cast<const double *>(b.data);
+  auto read_scalar = [&](double *out) -> dg_status {
+    DG_HIP(hipMemcpyAsync(pin.p, dscal, sizeof(double), hipMemcpyDeviceToHost, s));
+    DG_HIP(hipStreamSynchronize(s));
+    *out = *pin.p;
+    return DG_OK;
+  };
+  // ||b||
+  DG_HIP(norm2<double>(bp, false, n, part, dscal, s));
+  double nb = 0.0;
+  dg_status rc = read_scalar(&nb);
+  if (rc != DG_OK) return rc;
+  nb = std::sqrt(nb);
+  if (nb == 0.0) {
+    hipLaunchKernelGGL((fill_kernel<double>), dim3(grid), dim3(kRedThreads), 0, s, xp, 0.0, n);
+    DG_HIP(hipStreamSynchronize(s));
+    if (stats) *stats = st;
+    return DG_OK;
+  }
+  // true FP64 residual r64 = b - A x and its norm
+  auto true_residual = [&](double *rel) -> dg_status {
+    DG_HIP(launch_apply_any(op, xp, r64, false, s));
+    hipLaunchKernelGGL((sub_kernel<double>), dim3(grid), dim3(kRedThreads), 0, s, bp, r64, r64, n);
+    DG_HIP(norm2<double>(r64, false, n, part, dscal, s));
+    double v;
+    dg_status e = read_scalar(&v);
+    if (e != DG_OK) return e;
+    *rel = std::sqrt(v) / nb;
+    st.applies_f64 += 1;
+    return DG_OK;
+  };
+  double rel = 0.0;
+  dg_status result = DG_ERR_NOT_CONVERGED;
+  if (prm->mode == 0) {
+    // FP64 Jacobi-PCG; restarted from the true residual if the recurrence
+    // residual drifted below the tolerance first
+    PcgBuffers<double, double> buf;
+    if (!buf.alloc(ws, n)) return fail(DG_ERR_OOM, "solver workspace allocation failed");
+    for (int restart = 0; restart < 4; ++restart) {
+      int it = 0;
+      double rn = 0.0;
+      const int left = prm->max_iter - st.iters_inner;
+      if (left <= 0) break;
+      // solve A e = b - A x for the correction in place: run CG on x directly
+      rc = pcg<double, double>(op, bp, xp, false, prm->rel_tol * nb, left, prm->check_every, buf, pin, s, &it, &rn);
+      st.iters_inner += it;
+      st.applies_f64 += it + 1;
+      if (rc != DG_OK && rc != DG_ERR_NOT_CONVERGED) return rc;
+      if ((rc = true_residual(&rel)) != DG_OK) return rc;
+      if (rel <= prm->rel_tol) {
+        result = DG_OK;
+        break;
+      }
+    }
+  } else if (prm->mode == 2) {
+    float *e32 = static_cast<float *>(ws.get(n * sizeof(float)));
+    PcgBuffers<float, float> buf;
+    if (!e32 || !buf.alloc(ws, n)) return fail(DG_ERR_OOM, "solver workspace allocation failed");
+    rc = pcg_reliable(op, bp, xp, nb, prm->rel_tol, prm->rel_tol_inner, prm->max_iter, prm->check_every, buf, e32,
+                      r64, part, pin, s, st, &rel);
+    if (rc == DG_OK) result = DG_OK;
+    else if (rc != DG_ERR_NOT_CONVERGED) return rc;
+  } else {
+    // FP32 PCG on the correction equation inside FP64 iterative refinement
+    float *r32 = static_cast<float *>(ws.get(n * sizeof(float)));
+    float *d32 = static_cast<float *>(ws.get(n * sizeof(float)));
+    PcgBuffers<float, float> buf;
+    if (!r32 || !d32 || !buf.alloc(ws, n)) return fail(DG_ERR_OOM, "solver workspace allocation failed");
+    for (int outer = 0; outer <= prm->max_outer; ++outer) {
+      if ((rc = true_residual(&rel)) != DG_OK) return rc;
+      if (rel <= prm->rel_tol) {
+        result = DG_OK;
+        break;
+      }
+      if (outer == prm->max_outer || st.iters_inner >= prm->max_iter * prm->max_outer) break;
+      st.iters_outer += 1;
+      // r32 = r64 / ||r64||, d32 = 0
+      const double nr = rel * nb;
+      hipLaunchKernelGGL(scale_to_f32_kernel, dim3(grid), dim3(kRedThreads), 0, s, r64, 1.0 / nr, r32, n);
+      hipLaunchKernelGGL((fill_kernel<float>), dim3(grid), dim3(kRedThreads), 0, s, d32, 0.0f, n);
+      DG_HIP(hipGetLastError());
+      int it = 0;
+      double rn = 0.0;
+      rc = pcg<float, float>(op, r32, d32, true, prm->rel_tol_inner, prm->max_iter, prm->check_every, buf, pin, s,
+                             &it, &rn);
+      st.iters_inner += it;
+      st.applies_f32 += it;
+      if (rc != DG_OK && rc != DG_ERR_NOT_CONVERGED) return rc;
+      // x += ||r64|| * d32
+      hipLaunchKernelGGL(axpy_f32_kernel, dim3(grid), dim3(kRedThreads), 0, s, xp, nr, d32, n);
+      DG_HIP(hipGetLastError());
+    }
+  }
+  DG_HIP(hipStreamSynchronize(s));
+  st.final_rel_residual = rel;
+  st.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = st;
+  if (result != DG_OK) return fail(DG_ERR_NOT_CONVERGED, "solver did not reach the tolerance within its limits");
+  return DG_OK;
 }

@@ -1,0 +1,178 @@
+// solver_kernels.hpp -- BLAS-1 kernels of the CG solvers with deterministic
+// reductions (fixed partition, fixed summation order).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dgk {
+
+constexpr int kRedBlocks = 512;   // fixed partition of every reduction
+constexpr int kRedThreads = 256;
+
+// sum over the block in a fixed tree order; every thread gets the result
+template <typename Acc>
+__device__ __forceinline__ Acc block_sum(Acc v, Acc *sh)
+{
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  const Acc r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// the kRedBlocks partials of one reduction, summed in a fixed order
+template <typename Acc>
+__device__ __forceinline__ Acc reduce_partials(const Acc *part, int stride, Acc *sh)
+{
+  Acc v = Acc(0);
+  for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) v += part[i * stride];
+  return block_sum(v, sh);
+}
+
+template <typename Real, typename Acc>
+__global__ void __launch_bounds__(kRedThreads) dot_partial_kernel(const Real *__restrict__ x, const Real *__restrict__ y,
+                                                                  int64_t n, Acc *__restrict__ part)
+{
+  __shared__ Acc sh[kRedThreads];
+  Acc v = Acc(0);
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads)
+    v += (Acc)x[i] * (Acc)y[i];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+template <typename Acc>
+__global__ void __launch_bounds__(kRedThreads) finalize_kernel(const Acc *__restrict__ part, int count, Acc *out)
+{
+  __shared__ Acc sh[kRedThreads];
+  Acc v = Acc(0);
+  for (int i = threadIdx.x; i < count; i += kRedThreads) v += part[i];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) out[0] = v;
+}
+
+template <typename Real>
+__global__ void copy_kernel(const Real *__restrict__ a, Real *__restrict__ b, int64_t n)
+{
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+template <typename Real>
+__global__ void fill_kernel(Real *__restrict__ a, Real v, int64_t n)
+{
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+// c = a - b (c may alias b)
+template <typename Real>
+__global__ void sub_kernel(const Real *a, const Real *b, Real *c, int64_t n)
+{
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    c[i] = a[i] - b[i];
+}
+
+// partials of r.z and r.r with z = r / d, interleaved per block
+template <typename Real, typename Acc>
+__global__ void __launch_bounds__(kRedThreads) rz_partial_kernel(const Real *__restrict__ r, const Real *__restrict__ d,
+                                                                 int64_t n, Acc *__restrict__ part2)
+{
+  __shared__ Acc sh[kRedThreads];
+  Acc rz = Acc(0), rr = Acc(0);
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads) {
+    const Acc ri = (Acc)r[i];
+    rz += ri * (ri / (Acc)d[i]);
+    rr += ri * ri;
+  }
+  rz = block_sum(rz, sh);
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    part2[2 * blockIdx.x] = rz;
+    part2[2 * blockIdx.x + 1] = rr;
+  }
+}
+
+// alpha = rz / (p.q);  x += alpha p;  r -= alpha q;  partials of r.z, r.r
+template <typename Real, typename Acc>
+__global__ void __launch_bounds__(kRedThreads) cg_update_kernel(Real *__restrict__ x, Real *__restrict__ r,
+                                                                const Real *__restrict__ p, const Real *__restrict__ q,
+                                                                const Real *__restrict__ d, int64_t n,
+                                                                const Acc *__restrict__ pq_part, const Acc *scal,
+                                                                int cur, Acc *__restrict__ part2)
+{
+  __shared__ Acc sh[kRedThreads];
+  const Acc pq = reduce_partials(pq_part, 1, sh);
+  const Acc alpha = scal[cur] / pq;
+  Acc rz = Acc(0), rr = Acc(0);
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads) {
+    x[i] = (Real)((Acc)x[i] + alpha * (Acc)p[i]);
+    const Acc ri = (Acc)r[i] - alpha * (Acc)q[i];
+    r[i] = (Real)ri;
+    rz += ri * (ri / (Acc)d[i]);
+    rr += ri * ri;
+  }
+  rz = block_sum(rz, sh);
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    part2[2 * blockIdx.x] = rz;
+    part2[2 * blockIdx.x + 1] = rr;
+  }
+}
+
+// rz_new = r.z;  p = z + (rz_new / scal[cur]) p  (p = z when use_beta == 0);
+// block 0 stores rz_new in scal[1 - cur] and r.r in scal[2] (the other
+// blocks still read scal[cur], hence the ping-pong)
+template <typename Real, typename Acc>
+__global__ void __launch_bounds__(kRedThreads) cg_pupdate_kernel(Real *__restrict__ p, const Real *__restrict__ r,
+                                                                 const Real *__restrict__ d, int64_t n,
+                                                                 const Acc *__restrict__ part2, Acc *scal, int use_beta,
+                                                                 int cur)
+{
+  __shared__ Acc sh[kRedThreads];
+  const Acc rz = reduce_partials(part2, 2, sh);
+  const Acc rr = reduce_partials(part2 + 1, 2, sh);
+  const Acc beta = use_beta ? rz / scal[cur] : Acc(0);
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads) {
+    const Acc z = (Acc)r[i] / (Acc)d[i];
+    p[i] = use_beta ? (Real)(z + beta * (Acc)p[i]) : (Real)z;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[1 - cur] = rz;
+    scal[2] = rr;
+  }
+}
+
+// scal[cur] = r.z, scal[2] = r.r from interleaved partials
+template <typename Acc>
+__global__ void __launch_bounds__(kRedThreads) rz_finalize_kernel(const Acc *__restrict__ part2, Acc *scal, int cur)
+{
+  __shared__ Acc sh[kRedThreads];
+  const Acc rz = reduce_partials(part2, 2, sh);
+  const Acc rr = reduce_partials(part2 + 1, 2, sh);
+  if (threadIdx.x == 0) {
+    scal[cur] = rz;
+    scal[2] = rr;
+  }
+}
+
+__global__ inline void scale_to_f32_kernel(const double *__restrict__ a, double s, float *__restrict__ b, int64_t n)
+{
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = (float)(a[i] * s);
+}
+
+__global__ inline void axpy_f32_kernel(double *__restrict__ x, double a, const float *__restrict__ d, int64_t n)
+{
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] += a * (double)d[i];
+}
+
+}  // namespace dgk
