@@ -284,3 +284,61 @@ class Operator:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Continuous batching of mixed-precision solves (dg_batch_* of the C ABI).
+
+    Requests are admitted into free slots at any time; run(rounds) advances
+    every active request by that many CG iterations with one persistent
+    apply launch (plus three batched BLAS launches) per iteration; poll()
+    returns the requests that finished."""
+
+    def __init__(self, max_slots, torch_alloc=True):
+        self._alloc = TorchAllocator() if torch_alloc else None
+        h = ctypes.c_void_p()
+        check(lib().dg_batch_create(max_slots, ctypes.byref(self._alloc.struct) if self._alloc else None,
+                                    ctypes.byref(h)))
+        self._h = h
+        self.max_slots = max_slots
+        self._keep = {}
+
+    def admit(self, op, b, x, *, rel_tol=1e-8, refine_factor=0.1, max_iter=20000, check_every=10, stream=None):
+        p = SolveParams(2, rel_tol, refine_factor, max_iter, 1, check_every)
+        slot = ctypes.c_int(-1)
+        check(lib().dg_batch_admit(self._h, op.handle, vec(b), vec(x), ctypes.byref(p), ctypes.byref(slot),
+                                   _stream(stream)))
+        self._keep[slot.value] = (op, b, x)
+        return slot.value
+
+    def run(self, rounds, stream=None):
+        check(lib().dg_batch_run(self._h, rounds, _stream(stream)))
+
+    def poll(self):
+        cap = self.max_slots
+        slots = (ctypes.c_int * cap)()
+        stats = (SolveStats * cap)()
+        n = ctypes.c_int()
+        check(lib().dg_batch_poll(self._h, slots, stats, cap, ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            d = stats[i].as_dict()
+            out.append((slots[i], d))
+            self._keep.pop(slots[i], None)
+        return out
+
+    @property
+    def active(self):
+        return int(lib().dg_batch_active(self._h))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().dg_batch_destroy(self._h)
+        self._h = None
+        self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "dg_internal.hpp"
+#include "solver_host.hpp"
 #include "solver_kernels.hpp"
 
 namespace dgk {
@@ -166,12 +167,7 @@ dg_status pcg_reliable(dg_op *op, const double *b, double *x, double nb, double 
   };
   // FP64 residual r64 = b - A x, its relative norm, and r = r64 / ||b|| in FP32
   auto refresh = [&](double *rel) -> dg_status {
-    DG_HIP(launch_apply_any(op, x, r64, false, s));
-    hipLaunchKernelGGL((sub_kernel<double>), dim3(grid), dim3(kRedThreads), 0, s, b, r64, r64, n);
-    hipLaunchKernelGGL((dot_partial_kernel<double, double>), dim3(grid), dim3(kRedThreads), 0, s, r64, r64, n, dpart);
-    hipLaunchKernelGGL((finalize_kernel<double>), dim3(1), dim3(kRedThreads), 0, s, dpart, kRedBlocks, dscal);
-    hipLaunchKernelGGL(scale_to_f32_kernel, dim3(grid), dim3(kRedThreads), 0, s, r64, 1.0 / nb, r, n);
-    DG_HIP(hipGetLastError());
+    DG_HIP(rel_residual_async(op, b, x, r64, dpart, dscal, r, nb, s));
     double v;
     dg_status e2 = read(dscal, sizeof(double), &v);
     if (e2 != DG_OK) return e2;
@@ -184,11 +180,7 @@ dg_status pcg_reliable(dg_op *op, const double *b, double *x, double nb, double 
   if (rc != DG_OK) return rc;
   *rel_out = rel;
   if (rel <= tol) return DG_OK;
-  hipLaunchKernelGGL((fill_kernel<float>), dim3(grid), dim3(kRedThreads), 0, s, e, 0.0f, n);
-  hipLaunchKernelGGL((rz_partial_kernel<float, float>), dim3(grid), dim3(kRedThreads), 0, s, r, d, n, rz_part);
-  hipLaunchKernelGGL((cg_pupdate_kernel<float, float>), dim3(grid), dim3(kRedThreads), 0, s, p, r, d, n, rz_part,
-                     scal, 0, 0);
-  DG_HIP(hipGetLastError());
+  DG_HIP(start_direction_async(n, e, r, p, d, buf.part, s));
   int par = 1;
   double rlast = rel;
   st.iters_outer = 1;
@@ -210,18 +202,14 @@ dg_status pcg_reliable(dg_op *op, const double *b, double *x, double nb, double 
     if (!std::isfinite(r32)) return fail(DG_ERR_NOT_CONVERGED, "CG breakdown (non-finite residual)");
     if (r32 <= tol || r32 < delta * rlast || it == max_iter) {
       // refinement step: flush the correction, replace the residual
-      hipLaunchKernelGGL(axpy_f32_kernel, dim3(grid), dim3(kRedThreads), 0, s, x, nb, e, n);
-      hipLaunchKernelGGL((fill_kernel<float>), dim3(grid), dim3(kRedThreads), 0, s, e, 0.0f, n);
-      DG_HIP(hipGetLastError());
+      DG_HIP(flush_correction_async(n, x, nb, e, s));
       if ((rc = refresh(&rel)) != DG_OK) return rc;
       *rel_out = rel;
       if (rel <= tol) return DG_OK;
       st.iters_outer += 1;
       rlast = rel;
       // r.z of the replaced residual becomes the current r.z
-      hipLaunchKernelGGL((rz_partial_kernel<float, float>), dim3(grid), dim3(kRedThreads), 0, s, r, d, n, rz_part);
-      hipLaunchKernelGGL((rz_finalize_kernel<float>), dim3(1), dim3(kRedThreads), 0, s, rz_part, scal, par);
-      DG_HIP(hipGetLastError());
+      DG_HIP(restart_rz_async(n, r, d, buf.part, par, s));
     }
   }
   return DG_ERR_NOT_CONVERGED;

@@ -182,10 +182,12 @@ __device__ __forceinline__ int xcd_remap(int b, int G)
 #define DG_WG_WAVES 2
 #endif
 template <int N>
+inline constexpr int kTpb = (64 * DG_WG_WAVES >= N * N) ? 64 * DG_WG_WAVES : ((N * N + 63) / 64) * 64;
+
+template <int N, int TPB_ = kTpb<N>>
 struct Blocking {
   static constexpr int N2 = N * N, N3 = N2 * N;
-  static constexpr int TPB0 = 64 * DG_WG_WAVES;
-  static constexpr int TPB = TPB0 >= N2 ? TPB0 : ((N2 + 63) / 64) * 64;  // threads per workgroup
+  static constexpr int TPB = TPB_;           // threads per workgroup
   static constexpr int B = TPB / N2;         // cells per workgroup
   static constexpr int NT = B * N2;          // active threads
   static constexpr int WSZ = (2 * N3 > 10 * N2) ? 2 * N3 : 10 * N2;  // gradient / face scratch per cell
@@ -307,7 +309,7 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
                                                const Real *Q, Real *R, Real *W, int l, int cell,
                                                const int (&ci)[3], bool act, bool valid, Real (&nb)[2][N])
 {
-  constexpr int N2 = N * N, N3 = N2 * N;
+  constexpr int N2 = N * N;
   constexpr int t1 = (A == 0) ? 1 : 0, t2 = (A == 2) ? 1 : 2;
   constexpr Tables<N> T = kTab<N>;
   Real *X = W;            // [s][value, normal derivative] of the neighbour at Gauss-Lobatto face nodes p1 + N p2
@@ -470,20 +472,20 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
   __syncthreads();
 }
 
-template <int N, typename Real, int GK>
-__global__ void __launch_bounds__(Blocking<N>::TPB, (Occupancy<N, Real>::value))
-sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__restrict__ dst)
+// The fused pass over the cells of one batch (cells blk*B .. blk*B+B-1) by
+// a workgroup of TPB threads; smem holds B * (2 N^3 + WSZ) values.
+template <int N, typename Real, int GK, int TPB>
+__device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *__restrict__ src,
+                                            Real *__restrict__ dst, int blk, Real *smem)
 {
-  using BK = Blocking<N>;
-  constexpr int N2 = BK::N2, N3 = BK::N3, B = BK::B, NT = BK::NT, WSZ = BK::WSZ, TPB = BK::TPB;
+  using BK = Blocking<N, TPB>;
+  constexpr int N2 = BK::N2, N3 = BK::N3, B = BK::B, NT = BK::NT, WSZ = BK::WSZ;
   constexpr Tables<N> T = kTab<N>;
-  __shared__ Real smem[B * (2 * N3 + WSZ)];
 
   const int t = threadIdx.x;
   const bool act = t < NT;
   const int cb = act ? t / N2 : 0;
   const int l = act ? t - cb * N2 : 0;
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int cell0 = blk * B;
   const int cell = cell0 + cb;
   const bool valid = act && cell < op.ncells;
@@ -618,6 +620,15 @@ sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__r
   __syncthreads();
   const Real *Rall = smem + B * N3;
   for (int i = t; i < nhere * N3; i += TPB) dst[g0 + i] = Rall[i];
+}
+
+template <int N, typename Real, int GK>
+__global__ void __launch_bounds__(Blocking<N>::TPB, (Occupancy<N, Real>::value))
+sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__restrict__ dst)
+{
+  using BK = Blocking<N>;
+  __shared__ Real smem[BK::B * (2 * BK::N3 + BK::WSZ)];
+  apply_batch<N, Real, GK, BK::TPB>(op, src, dst, xcd_remap(blockIdx.x, gridDim.x), smem);
 }
 
 // ---------------------------------------------------------------------------

@@ -36,16 +36,27 @@ __device__ __forceinline__ Acc reduce_partials(const Acc *part, int stride, Acc 
   return block_sum(v, sh);
 }
 
+// The chunk-th piece of a reduction (chunk in [0, kRedBlocks)) covers the
+// elements chunk*T + t + j*kRedBlocks*T; the kernels below run one chunk per
+// workgroup, the batched kernels one chunk of one request per workgroup, so
+// a request's sums do not depend on what else shares the launch.
+template <typename Real, typename Acc>
+__device__ __forceinline__ void dot_partial_body(const Real *__restrict__ x, const Real *__restrict__ y, int64_t n,
+                                                 Acc *__restrict__ part, int chunk, Acc *sh)
+{
+  Acc v = Acc(0);
+  for (int64_t i = (int64_t)chunk * kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads)
+    v += (Acc)x[i] * (Acc)y[i];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) part[chunk] = v;
+}
+
 template <typename Real, typename Acc>
 __global__ void __launch_bounds__(kRedThreads) dot_partial_kernel(const Real *__restrict__ x, const Real *__restrict__ y,
                                                                   int64_t n, Acc *__restrict__ part)
 {
   __shared__ Acc sh[kRedThreads];
-  Acc v = Acc(0);
-  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads)
-    v += (Acc)x[i] * (Acc)y[i];
-  v = block_sum(v, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = v;
+  dot_partial_body(x, y, n, part, blockIdx.x, sh);
 }
 
 template <typename Acc>
@@ -102,17 +113,15 @@ __global__ void __launch_bounds__(kRedThreads) rz_partial_kernel(const Real *__r
 
 // alpha = rz / (p.q);  x += alpha p;  r -= alpha q;  partials of r.z, r.r
 template <typename Real, typename Acc>
-__global__ void __launch_bounds__(kRedThreads) cg_update_kernel(Real *__restrict__ x, Real *__restrict__ r,
-                                                                const Real *__restrict__ p, const Real *__restrict__ q,
-                                                                const Real *__restrict__ d, int64_t n,
-                                                                const Acc *__restrict__ pq_part, const Acc *scal,
-                                                                int cur, Acc *__restrict__ part2)
+__device__ __forceinline__ void cg_update_body(Real *__restrict__ x, Real *__restrict__ r, const Real *__restrict__ p,
+                                               const Real *__restrict__ q, const Real *__restrict__ d, int64_t n,
+                                               const Acc *__restrict__ pq_part, const Acc *scal, int cur,
+                                               Acc *__restrict__ part2, int chunk, Acc *sh)
 {
-  __shared__ Acc sh[kRedThreads];
   const Acc pq = reduce_partials(pq_part, 1, sh);
   const Acc alpha = scal[cur] / pq;
   Acc rz = Acc(0), rr = Acc(0);
-  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads) {
+  for (int64_t i = (int64_t)chunk * kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads) {
     x[i] = (Real)((Acc)x[i] + alpha * (Acc)p[i]);
     const Acc ri = (Acc)r[i] - alpha * (Acc)q[i];
     r[i] = (Real)ri;
@@ -122,14 +131,43 @@ __global__ void __launch_bounds__(kRedThreads) cg_update_kernel(Real *__restrict
   rz = block_sum(rz, sh);
   rr = block_sum(rr, sh);
   if (threadIdx.x == 0) {
-    part2[2 * blockIdx.x] = rz;
-    part2[2 * blockIdx.x + 1] = rr;
+    part2[2 * chunk] = rz;
+    part2[2 * chunk + 1] = rr;
   }
 }
 
+template <typename Real, typename Acc>
+__global__ void __launch_bounds__(kRedThreads) cg_update_kernel(Real *__restrict__ x, Real *__restrict__ r,
+                                                                const Real *__restrict__ p, const Real *__restrict__ q,
+                                                                const Real *__restrict__ d, int64_t n,
+                                                                const Acc *__restrict__ pq_part, const Acc *scal,
+                                                                int cur, Acc *__restrict__ part2)
+{
+  __shared__ Acc sh[kRedThreads];
+  cg_update_body(x, r, p, q, d, n, pq_part, scal, cur, part2, blockIdx.x, sh);
+}
+
 // rz_new = r.z;  p = z + (rz_new / scal[cur]) p  (p = z when use_beta == 0);
-// block 0 stores rz_new in scal[1 - cur] and r.r in scal[2] (the other
-// blocks still read scal[cur], hence the ping-pong)
+// chunk 0 stores rz_new in scal[1 - cur] and r.r in scal[2] (the other
+// chunks still read scal[cur], hence the ping-pong)
+template <typename Real, typename Acc>
+__device__ __forceinline__ void cg_pupdate_body(Real *__restrict__ p, const Real *__restrict__ r,
+                                                const Real *__restrict__ d, int64_t n, const Acc *__restrict__ part2,
+                                                Acc *scal, int use_beta, int cur, int chunk, Acc *sh)
+{
+  const Acc rz = reduce_partials(part2, 2, sh);
+  const Acc rr = reduce_partials(part2 + 1, 2, sh);
+  const Acc beta = use_beta ? rz / scal[cur] : Acc(0);
+  for (int64_t i = (int64_t)chunk * kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads) {
+    const Acc z = (Acc)r[i] / (Acc)d[i];
+    p[i] = use_beta ? (Real)(z + beta * (Acc)p[i]) : (Real)z;
+  }
+  if (chunk == 0 && threadIdx.x == 0) {
+    scal[1 - cur] = rz;
+    scal[2] = rr;
+  }
+}
+
 template <typename Real, typename Acc>
 __global__ void __launch_bounds__(kRedThreads) cg_pupdate_kernel(Real *__restrict__ p, const Real *__restrict__ r,
                                                                  const Real *__restrict__ d, int64_t n,
@@ -137,17 +175,7 @@ __global__ void __launch_bounds__(kRedThreads) cg_pupdate_kernel(Real *__restric
                                                                  int cur)
 {
   __shared__ Acc sh[kRedThreads];
-  const Acc rz = reduce_partials(part2, 2, sh);
-  const Acc rr = reduce_partials(part2 + 1, 2, sh);
-  const Acc beta = use_beta ? rz / scal[cur] : Acc(0);
-  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads) {
-    const Acc z = (Acc)r[i] / (Acc)d[i];
-    p[i] = use_beta ? (Real)(z + beta * (Acc)p[i]) : (Real)z;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    scal[1 - cur] = rz;
-    scal[2] = rr;
-  }
+  cg_pupdate_body(p, r, d, n, part2, scal, use_beta, cur, blockIdx.x, sh);
 }
 
 // scal[cur] = r.z, scal[2] = r.r from interleaved partials
@@ -163,13 +191,13 @@ __global__ void __launch_bounds__(kRedThreads) rz_finalize_kernel(const Acc *__r
   }
 }
 
-__global__ inline void scale_to_f32_kernel(const double *__restrict__ a, double s, float *__restrict__ b, int64_t n)
+static __global__ void scale_to_f32_kernel(const double *__restrict__ a, double s, float *__restrict__ b, int64_t n)
 {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     b[i] = (float)(a[i] * s);
 }
 
-__global__ inline void axpy_f32_kernel(double *__restrict__ x, double a, const float *__restrict__ d, int64_t n)
+static __global__ void axpy_f32_kernel(double *__restrict__ x, double a, const float *__restrict__ d, int64_t n)
 {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     x[i] += a * (double)d[i];
