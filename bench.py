@@ -107,7 +107,12 @@ def main():
     ap.add_argument("--degree", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["f64", "f32"], default=None)
-    ap.add_argument("--solve-reps", type=int, default=0)
+    ap.add_argument("--solve-reps", type=int, default=3,
+                    help="repeated config-4 solves per mode for the latency percentiles (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests in the serving trace (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-budget-gib", type=float, default=128.0, help="HBM admission budget")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -154,6 +159,9 @@ def main():
     solve = None
     if args.solve_reps > 0:
         solve = bench_solve(dg, torch, np, synth, args.solve_reps)
+    serving = None
+    if args.serve_requests > 0:
+        serving = bench_serve(synth, args.serve_requests, args.serve_rate, args.serve_budget_gib)
 
     head = res.get("f64") or res.get("f32")
     headp = "f64" if "f64" in res else "f32"
@@ -186,6 +194,8 @@ def main():
                         "speedup_vs_fp64": r["dofs"] / head["dofs"]}
     if solve:
         line["solve"] = solve
+    if serving:
+        line["serve"] = serving
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(N, k)
     print(json.dumps(line), flush=True)
@@ -222,6 +232,19 @@ def bench_solve(dg, torch, np, synth, reps):
     out["speedup_mixed_vs_fp64_p50"] = out["fp64"]["p50_ms"] / out["mixed"]["p50_ms"]
     op.close()
     return out
+
+
+def bench_serve(synth, n_requests, rate, budget_gib):
+    """Config 5: open-loop Poisson arrivals, edge cells log-uniform in [4,48],
+    degree uniform in 2..7, half curved; mixed-precision solves to 1e-8
+    admitted by HBM footprint into one continuously batched solver."""
+    from paper_1711_03590_amd import serve
+    trace = synth.request_trace(n_requests, rate=rate, seed=5005)
+    rep = serve.serve(trace, budget_bytes=int(budget_gib * (1 << 30)), max_slots=32, rounds_per_step=10,
+                      rel_tol=1e-8)
+    rep["workload"] = (f"{n_requests} requests, Poisson arrivals at {rate:g}/s, edge cells log-uniform in [4,48], "
+                       "degree uniform in 2..7, 50% curved, seeded uniform RHS, mixed CG to 1e-8")
+    return rep
 
 
 if __name__ == "__main__":
