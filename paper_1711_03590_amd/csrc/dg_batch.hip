@@ -53,7 +53,7 @@ template <int N>
 constexpr int batch_lds()
 {
   using BK = Blocking<N, kBatchTpb>;
-  return BK::B * (2 * BK::N3 + BK::WSZ);
+  return BK::SMEM;
 }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int kBatchLds = cmax(cmax(cmax(batch_lds<3>(), batch_lds<4>()), cmax(batch_lds<5>(), batch_lds<6>())),

@@ -191,6 +191,7 @@ struct Blocking {
   static constexpr int B = TPB / N2;         // cells per workgroup
   static constexpr int NT = B * N2;          // active threads
   static constexpr int WSZ = (2 * N3 > 10 * N2) ? 2 * N3 : 10 * N2;  // gradient / face scratch per cell
+  static constexpr int SMEM = B * (2 * N3 + WSZ);  // shared memory in Real units
 };
 
 // Workgroups per CU that the LDS footprint allows (160 KiB per CU).  With
@@ -205,7 +206,7 @@ struct Blocking {
 #endif
 template <int N, typename Real>
 struct Occupancy {
-  static constexpr int lds = Blocking<N>::B * (2 * Blocking<N>::N3 + Blocking<N>::WSZ) * (int)sizeof(Real);
+  static constexpr int lds = Blocking<N>::SMEM * (int)sizeof(Real);
   static constexpr int wgs = 163840 / lds;
   static constexpr int waves = wgs * (Blocking<N>::TPB / 64) / 4;
   static constexpr int cap = sizeof(Real) == 8 ? DG_MAX_WAVES_F64 : DG_MAX_WAVES_F32;
@@ -274,25 +275,22 @@ __device__ __forceinline__ void end_derivatives(const Real (&v)[N], Real &lo, Re
   hi = so - se;
 }
 
-// The two neighbours' normal lines through face point l for direction A
-// (zeros where there is no neighbour); issued ahead of their use so that the
-// loads overlap the preceding phase.
+// The two neighbours' normal lines through face point l for direction A;
+// issued ahead of their use so that the loads overlap the preceding phase.
 template <int N, typename Real, int A>
 __device__ __forceinline__ void load_neighbour_lines(const OpView<Real> &op, const Real *__restrict__ src,
-                                                     int cell, int l, const int (&ci)[3], bool valid,
-                                                     Real (&nb)[2][N])
+                                                     int cell, int l, const int (&ci)[3], Real (&nb)[2][N])
 {
+  // branch-free: a missing neighbour reads the cell itself (the values are
+  // then ignored), so the loads can stay in flight across later phases
   constexpr int N3 = N * N * N;
   const int64_t cstride = (A == 0) ? 1 : (A == 1 ? (int64_t)op.ncell[0] : (int64_t)op.ncell[0] * op.ncell[1]);
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const int cn = ci[A] + (s ? 1 : -1);
-    if (valid && cn >= 0 && cn < op.ncell[A]) {
-      load_line<N, A>(src + (int64_t)(cell + (s ? cstride : -cstride)) * N3, l, nb[s]);
-    } else {
-#pragma unroll
-      for (int m = 0; m < N; ++m) nb[s][m] = Real(0);
-    }
+    const bool inside = cn >= 0 && cn < op.ncell[A];
+    const int64_t nbc = inside ? (int64_t)cell + (s ? cstride : -cstride) : (int64_t)cell;
+    load_line<N, A>(src + nbc * N3, l, nb[s]);
   }
 }
 
@@ -325,18 +323,15 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
     const int cn = ci[A] + (s ? 1 : -1);
     interior[s] = valid && cn >= 0 && cn < op.ncell[A];
   }
+  Real jg[2][3], cds[2];
+  face_geometry<N, Real, GK, A>(op, ci, 0, l, jg[0], cds[0]);
+  face_geometry<N, Real, GK, A>(op, ci, 1, l, jg[1], cds[1]);
   // S1: own value and reference normal derivative at this face point (the
   // Gauss-point data is tangentially at the face's Gauss points already);
   // the neighbour's value and normal derivative at the Gauss-Lobatto nodes of
-  // the shared face from its prefetched normal line: end node (nodal basis)
-  // and D_f of Eq. (7).  The face geometry used in S6 is requested here.
+  // the shared face: end node (nodal basis) and D_f of Eq. (7)
   Real um[2], dm[2];
-  Real jg[2][3] = {{Real(0), Real(0), Real(0)}, {Real(0), Real(0), Real(0)}}, cds[2] = {Real(0), Real(0)};
   if (act) {
-    if (valid) {
-      face_geometry<N, Real, GK, A>(op, ci, 0, l, jg[0], cds[0]);
-      face_geometry<N, Real, GK, A>(op, ci, 1, l, jg[1], cds[1]);
-    }
     Real v[N];
     load_line<N, A>(Q, l, v);
     end_values<N>(v, um[0], um[1]);
@@ -355,9 +350,7 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
   }
   __syncthreads();
   // the next direction's neighbour lines, consumed by its S1
-  if constexpr (A < 2) {
-    if (act) load_neighbour_lines<N, Real, A + 1>(op, src, cell, l, ci, valid, nb);
-  }
+  if constexpr (A < 2) load_neighbour_lines<N, Real, A + 1>(op, src, cell, l, ci, nb);
   // S2: neighbour traces, basis change along t1 (one line per job)
   // (2N jobs; with N^2 < 2N threads per cell a thread takes several)
   if (act) for (int jb = l; jb < 2 * N; jb += N2) {
@@ -487,8 +480,10 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
   const int cb = act ? t / N2 : 0;
   const int l = act ? t - cb * N2 : 0;
   const int cell0 = blk * B;
-  const int cell = cell0 + cb;
-  const bool valid = act && cell < op.ncells;
+  // cells past the end of the mesh (last workgroup) compute on a copy of the
+  // last cell and are never written; all global loads stay unconditional
+  const int cell = min(cell0 + cb, op.ncells - 1);
+  const bool valid = act && cell0 + cb < op.ncells;
   const int nhere = min(B, op.ncells - cell0);
   Real *Q = smem + cb * N3;              // values at the Gauss points (kept to the end of the faces)
   Real *R = smem + B * N3 + cb * N3;     // residual at the Gauss points
@@ -528,15 +523,10 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
     Real gbuf[2][10];
     auto load_geometry = [&](int k, Real (&gb)[10]) {
       if constexpr (GK == CURVED) {
-        if (valid) {
-          const int64_t ix = (int64_t)cell * N3 + l + k * N2;
-          const int64_t cs = op.g.cell_stride;
+        const int64_t ix = (int64_t)cell * N3 + l + k * N2;
+        const int64_t cs = op.g.cell_stride;
 #pragma unroll
-          for (int m = 0; m < 10; ++m) gb[m] = op.g.cell[m * cs + ix];
-        } else {
-#pragma unroll
-          for (int m = 0; m < 10; ++m) gb[m] = Real(0);
-        }
+        for (int m = 0; m < 10; ++m) gb[m] = op.g.cell[m * cs + ix];
       }
     };
     load_geometry(0, gbuf[0]);
@@ -558,7 +548,7 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
       } else {
         Real f;
         if constexpr (GK == AFFINE_VAR) {
-          f = valid ? op.g.cell[(int64_t)cell * N3 + p] : Real(0);
+          f = op.g.cell[(int64_t)cell * N3 + p];
         } else {
           const int i1 = l % N, i2 = l / N;
           Real w1 = Real(0), w2 = Real(0);
@@ -584,7 +574,7 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
   // transposed collocation derivatives along x and y summed into R; the
   // x-direction neighbour lines for the face phase are requested first
   Real nb[2][N];
-  if (act) load_neighbour_lines<N, Real, 0>(op, src, cell, l, ci, valid, nb);
+  load_neighbour_lines<N, Real, 0>(op, src, cell, l, ci, nb);
   if (act) {
     Real v[N], r[N], q[N];
     load_line<N, 0>(G0, l, v);
@@ -627,7 +617,7 @@ __global__ void __launch_bounds__(Blocking<N>::TPB, (Occupancy<N, Real>::value))
 sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__restrict__ dst)
 {
   using BK = Blocking<N>;
-  __shared__ Real smem[BK::B * (2 * BK::N3 + BK::WSZ)];
+  __shared__ Real smem[BK::SMEM];
   apply_batch<N, Real, GK, BK::TPB>(op, src, dst, xcd_remap(blockIdx.x, gridDim.x), smem);
 }
 
