@@ -178,6 +178,10 @@ __device__ __forceinline__ int xcd_remap(int b, int G)
   return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + k;
 }
 
+// quadrature-point planes of stored cell geometry held in flight per thread
+#ifndef DG_GEO_BUFS
+#define DG_GEO_BUFS 3
+#endif
 #ifndef DG_WG_WAVES
 #define DG_WG_WAVES 2
 #endif
@@ -494,9 +498,34 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
   ci[1] = (cell / op.ncell[0]) % op.ncell[1];
   ci[2] = cell / (op.ncell[0] * op.ncell[1]);
 
-  // (a) gather the workgroup's cells (coalesced)
+  // (a) gather the workgroup's cells (coalesced), and request the stored
+  // geometry of the first two quadrature-point planes of this thread's
+  // z-line behind it: those loads stay in flight through the basis change
   const int64_t g0 = (int64_t)cell0 * N3;
-  for (int i = t; i < B * N3; i += TPB) smem[i] = (i < nhere * N3) ? src[g0 + i] : Real(0);
+  constexpr int GI = (B * N3 + TPB - 1) / TPB;
+  Real gv[GI];
+#pragma unroll
+  for (int j = 0; j < GI; ++j) gv[j] = src[g0 + min(t + j * TPB, nhere * N3 - 1)];
+  __builtin_amdgcn_sched_barrier(0);  // keep the gather ahead of the geometry loads
+  constexpr int NB = (DG_GEO_BUFS < N) ? DG_GEO_BUFS : N;
+  Real gbuf[NB][10];
+  auto load_geometry = [&](int k, Real (&gb)[10]) {
+    if constexpr (GK == CURVED) {
+      const int64_t ix = (int64_t)cell * N3 + l + k * N2;
+      const int64_t cs = op.g.cell_stride;
+#pragma unroll
+      for (int m = 0; m < 10; ++m) gb[m] = op.g.cell[m * cs + ix];
+    }
+  };
+#pragma unroll
+  for (int k = 0; k < NB; ++k) load_geometry(k, gbuf[k]);
+  // (slots past B N^3 fall into R, which is written before it is read)
+  static_assert(GI * TPB <= 2 * B * N3, "gather overrun");
+#pragma unroll
+  for (int j = 0; j < GI; ++j) {
+    const int i = t + j * TPB;
+    smem[i] = i < nhere * N3 ? gv[j] : Real(0);
+  }
   __syncthreads();
 
   // (b) basis change to the Gauss points (Eq. (6), right factor)
@@ -515,36 +544,26 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
 
   // (c) cell quadrature-point operation along this thread's z-line; the
   // stored geometry (J^{-T} and c det J w per point) is software-pipelined
-  // one point ahead so that at most two points' worth of it is in registers
+  // DG_GEO_BUFS points ahead in as many register buffers
   if (act) {
     Real qz[N], dz[N], t2v[N];
     load_line<N, 2>(Q, l, qz);
     eo_apply<N, M_DCO>(qz, dz);
-    Real gbuf[2][10];
-    auto load_geometry = [&](int k, Real (&gb)[10]) {
-      if constexpr (GK == CURVED) {
-        const int64_t ix = (int64_t)cell * N3 + l + k * N2;
-        const int64_t cs = op.g.cell_stride;
-#pragma unroll
-        for (int m = 0; m < 10; ++m) gb[m] = op.g.cell[m * cs + ix];
-      }
-    };
-    load_geometry(0, gbuf[0]);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       const int p = l + k * N2;
       const Real g[3] = {G0[p], G1[p], dz[k]};
       Real o[3];
       if constexpr (GK == CURVED) {
-        const Real *jt = gbuf[k & 1];
-        const Real f = gbuf[k & 1][9];
-        if (k + 1 < N) load_geometry(k + 1, gbuf[(k + 1) & 1]);
-        __builtin_amdgcn_sched_barrier(0);
+        const Real *jt = gbuf[k % NB];
+        const Real f = gbuf[k % NB][9];
         Real gx[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) gx[a] = f * (jt[3 * a] * g[0] + jt[3 * a + 1] * g[1] + jt[3 * a + 2] * g[2]);
 #pragma unroll
         for (int b = 0; b < 3; ++b) o[b] = jt[b] * gx[0] + jt[3 + b] * gx[1] + jt[6 + b] * gx[2];
+        __builtin_amdgcn_sched_barrier(0);
+        if (k + NB < N) load_geometry(k + NB, gbuf[k % NB]);
       } else {
         Real f;
         if constexpr (GK == AFFINE_VAR) {
