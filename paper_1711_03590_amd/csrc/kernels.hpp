@@ -7,25 +7,28 @@
 // one thread to one 1D line of each cell (N^2 lines per sweep direction).
 // Per cell, in one pass (Algorithm 1 steps (ii)-(iv) fused, Design Choice 2):
 //   (a) gather the cell's N^3 coefficients into LDS (coalesced block copy);
-//   (b) basis change to the Gauss points, S x S x S, then the collocation
-//       derivative Dco along x, y, z (Sec. 2, Eq. (6)), every 1D matvec done
-//       with the even-odd decomposition (Sec. 3.3, Eq. (8));
-//   (c) own-side traces of all six faces: values and reference gradients at
-//       the face points, read off the quadrature-point data with the Gauss
-//       Lagrange end values (face-normal interpolation of Eq. (7) on the
-//       collocation basis: the tangential directions are already at the
-//       face's Gauss points);
-//   (d) cell quadrature-point operation (Algorithm 1 step (c)):
-//       t = J^{-1} (c det J w) J^{-T} grad_xi u, then the transposed collocation
-//       derivative sums the three components into the residual;
-//   (e) per face direction: the neighbour's trace from its Gauss-Lobatto
-//       coefficients (value = end node, normal derivative by D_f of Eq. (7)),
-//       then a 2D basis change S x S (plus D for the tangential derivative)
-//       to the face Gauss points; numerical flux of Eq. (2) with the stored
+//   (b) basis change to the Gauss points, S x S x S (Sec. 2, Eq. (6)), every
+//       1D matvec done with the even-odd decomposition (Sec. 3.3, Eq. (8));
+//   (c) per face direction: own-side value and reference normal derivative
+//       at the face points, read off the Gauss-point data with the Gauss
+//       Lagrange end values (the tangential directions already sit at the
+//       face's Gauss points); the neighbour's trace from its Gauss-Lobatto
+//       coefficients (value = end node, normal derivative by D_f of
+//       Eq. (7)), then a 2D basis change S x S to the face Gauss points and
+//       the collocation derivative along the face for the tangential
+//       gradient; numerical flux of Eq. (2) with the stored
 //       normal-times-inverse-Jacobian j (Design Choice 5); own-side
 //       integration back onto the quadrature-point residual;
-//   (f) transposed basis change S^T x S^T x S^T and one coalesced write of
+//   (d) cell quadrature-point operation (Algorithm 1 step (c)): collocation
+//       derivatives Dco along x, y, z, t = J^{-1} (c det J w) J^{-T} grad_xi u,
+//       then the transposed derivatives sum the three components into the
+//       residual;
+//   (e) transposed basis change S^T x S^T x S^T and one coalesced write of
 //       the cell's dst block (cells set, never add: Sec. 2.1).
+// The faces come before the cell integrals so that the neighbour blocks are
+// read while the workgroups that own them, dispatched at about the same
+// time, have just read them too (L2 hits rather than fabric traffic); the
+// stored cell geometry, the bulk of the traffic, streams in behind.
 // No atomics: every dst entry is written by exactly one thread, so the
 // result is deterministic.  Neighbour blocks are re-read from L2/MALL.
 #pragma once
@@ -182,6 +185,10 @@ __device__ __forceinline__ int xcd_remap(int b, int G)
 #ifndef DG_GEO_BUFS
 #define DG_GEO_BUFS 3
 #endif
+// of which requested already during the last face direction
+#ifndef DG_GEO_PRE
+#define DG_GEO_PRE 1
+#endif
 #ifndef DG_WG_WAVES
 #define DG_WG_WAVES 2
 #endif
@@ -306,10 +313,10 @@ __device__ __forceinline__ void load_neighbour_lines(const OpView<Real> &op, con
 //   [[u]] = u- - u+, {{grad u}} = (grad u- + grad u+)/2; the average's
 //   tangential part is the tangential derivative of V = u- + u+ on the face
 //   (V = 2 u- on a Dirichlet face, where u+ = -u- but grad u+ = grad u-).
-template <int N, typename Real, int GK, int A>
-__device__ __forceinline__ void face_direction(const OpView<Real> &op, const Real *__restrict__ src,
-                                               const Real *Q, Real *R, Real *W, int l, int cell,
-                                               const int (&ci)[3], bool act, bool valid, Real (&nb)[2][N])
+template <int N, typename Real, int GK, int A, typename Next>
+__device__ __forceinline__ void face_direction(const OpView<Real> &op, const Real *Q, Real *R, Real *W, int l,
+                                               const int (&ci)[3], bool act, bool valid, const Real (&nb)[2][N],
+                                               Next &&next)
 {
   constexpr int N2 = N * N;
   constexpr int t1 = (A == 0) ? 1 : 0, t2 = (A == 2) ? 1 : 2;
@@ -353,8 +360,9 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
     X[3 * N2 + l] = der1;
   }
   __syncthreads();
-  // the next direction's neighbour lines, consumed by its S1
-  if constexpr (A < 2) load_neighbour_lines<N, Real, A + 1>(op, src, cell, l, ci, nb);
+  // loads for what follows (the next direction's neighbour lines, or the
+  // first planes of cell geometry), in flight through the rest of the faces
+  next();
   // S2: neighbour traces, basis change along t1 (one line per job)
   // (2N jobs; with N^2 < 2N threads per cell a thread takes several)
   if (act) for (int jb = l; jb < 2 * N; jb += N2) {
@@ -498,28 +506,19 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
   ci[1] = (cell / op.ncell[0]) % op.ncell[1];
   ci[2] = cell / (op.ncell[0] * op.ncell[1]);
 
-  // (a) gather the workgroup's cells (coalesced), and request the stored
-  // geometry of the first two quadrature-point planes of this thread's
-  // z-line behind it: those loads stay in flight through the basis change
+  // (a) gather the workgroup's cells (coalesced), and request the
+  // x-direction neighbour lines behind it: the faces come first, while the
+  // neighbouring workgroups, started at about the same time, have just read
+  // the same blocks (they are then still in L2)
   const int64_t g0 = (int64_t)cell0 * N3;
   constexpr int GI = (B * N3 + TPB - 1) / TPB;
   Real gv[GI];
 #pragma unroll
   for (int j = 0; j < GI; ++j) gv[j] = src[g0 + min(t + j * TPB, nhere * N3 - 1)];
-  __builtin_amdgcn_sched_barrier(0);  // keep the gather ahead of the geometry loads
-  constexpr int NB = (DG_GEO_BUFS < N) ? DG_GEO_BUFS : N;
-  Real gbuf[NB][10];
-  auto load_geometry = [&](int k, Real (&gb)[10]) {
-    if constexpr (GK == CURVED) {
-      const int64_t ix = (int64_t)cell * N3 + l + k * N2;
-      const int64_t cs = op.g.cell_stride;
-#pragma unroll
-      for (int m = 0; m < 10; ++m) gb[m] = op.g.cell[m * cs + ix];
-    }
-  };
-#pragma unroll
-  for (int k = 0; k < NB; ++k) load_geometry(k, gbuf[k]);
-  // (slots past B N^3 fall into R, which is written before it is read)
+  __builtin_amdgcn_sched_barrier(0);  // keep the gather ahead of the neighbour loads
+  Real nb[2][N];
+  load_neighbour_lines<N, Real, 0>(op, src, cell, l, ci, nb);
+  // (slots past B N^3 fall into R, which is cleared before it is used)
   static_assert(GI * TPB <= 2 * B * N3, "gather overrun");
 #pragma unroll
   for (int j = 0; j < GI; ++j) {
@@ -530,21 +529,47 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
 
   // (b) basis change to the Gauss points (Eq. (6), right factor)
   if (act) sweep<N, 0, M_S>(Q, Q, l);
+  for (int i = t; i < B * N3; i += TPB) smem[B * N3 + i] = Real(0);  // R
   __syncthreads();
   if (act) sweep<N, 1, M_S>(Q, Q, l);
   __syncthreads();
   if (act) sweep<N, 2, M_S>(Q, Q, l);
   __syncthreads();
-  // collocation derivative along x and y (z is taken in registers below)
+
+  // (c) face terms, direction by direction, into R; the stored cell geometry
+  // of the first planes is requested during the last direction
+  constexpr int NB = (DG_GEO_BUFS < N) ? DG_GEO_BUFS : N;
+  Real gbuf[NB][10];
+  auto load_geometry = [&](int k, Real (&gb)[10]) {
+    if constexpr (GK == CURVED) {
+      const int64_t ix = (int64_t)cell * N3 + l + k * N2;
+      const int64_t cs = op.g.cell_stride;
+#pragma unroll
+      for (int m = 0; m < 10; ++m) gb[m] = op.g.cell[m * cs + ix];
+    }
+  };
+  face_direction<N, Real, GK, 0>(op, Q, R, W, l, ci, act, valid, nb,
+                                 [&] { load_neighbour_lines<N, Real, 1>(op, src, cell, l, ci, nb); });
+  face_direction<N, Real, GK, 1>(op, Q, R, W, l, ci, act, valid, nb,
+                                 [&] { load_neighbour_lines<N, Real, 2>(op, src, cell, l, ci, nb); });
+  constexpr int PRE = (DG_GEO_PRE < NB) ? DG_GEO_PRE : NB;
+  face_direction<N, Real, GK, 2>(op, Q, R, W, l, ci, act, valid, nb, [&] {
+#pragma unroll
+    for (int k = 0; k < PRE; ++k) load_geometry(k, gbuf[k]);
+  });
+#pragma unroll
+  for (int k = PRE; k < NB; ++k) load_geometry(k, gbuf[k]);
+
+  // (d) cell integrals: collocation derivatives along x and y (z is taken
+  // in registers below), then the quadrature-point operation along this
+  // thread's z-line with the stored geometry (J^{-T} and c det J w per
+  // point) software-pipelined NB planes ahead, then the transposed
+  // derivatives, all summed into R
   if (act) {
     sweep<N, 0, M_DCO>(Q, G0, l);
     sweep<N, 1, M_DCO>(Q, G1, l);
   }
   __syncthreads();
-
-  // (c) cell quadrature-point operation along this thread's z-line; the
-  // stored geometry (J^{-T} and c det J w per point) is software-pipelined
-  // DG_GEO_BUFS points ahead in as many register buffers
   if (act) {
     Real qz[N], dz[N], t2v[N];
     load_line<N, 2>(Q, l, qz);
@@ -585,15 +610,14 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
       G1[p] = o[1];
       t2v[k] = o[2];
     }
-    Real rz[N];
+    Real rz[N], q[N];
     eo_apply<N, M_DCOT>(t2v, rz);
-    store_line<N, 2>(R, l, rz);
+    load_line<N, 2>(R, l, q);
+#pragma unroll
+    for (int m = 0; m < N; ++m) q[m] += rz[m];
+    store_line<N, 2>(R, l, q);
   }
   __syncthreads();
-  // transposed collocation derivatives along x and y summed into R; the
-  // x-direction neighbour lines for the face phase are requested first
-  Real nb[2][N];
-  load_neighbour_lines<N, Real, 0>(op, src, cell, l, ci, nb);
   if (act) {
     Real v[N], r[N], q[N];
     load_line<N, 0>(G0, l, v);
@@ -614,11 +638,6 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
     store_line<N, 1>(R, l, q);
   }
   __syncthreads();
-
-  // (d) face terms, direction by direction (W is free again)
-  face_direction<N, Real, GK, 0>(op, src, Q, R, W, l, cell, ci, act, valid, nb);
-  face_direction<N, Real, GK, 1>(op, src, Q, R, W, l, cell, ci, act, valid, nb);
-  face_direction<N, Real, GK, 2>(op, src, Q, R, W, l, cell, ci, act, valid, nb);
 
   // (e) back to the Gauss-Lobatto basis (transposed basis change) and write
   if (act) sweep<N, 0, M_ST>(R, R, l);
