@@ -4,12 +4,15 @@ Workload: 32^3 hexahedra on the unit cube deformed by the sine map
 (amplitude 0.05), degree k = 4 (4,096,000 DoFs), Jacobians stored at every
 quadrature point, seeded uniform [-1,1] source.  A step is one operator
 evaluation y = A u over the whole mesh (the fused cell + face pass).  The
-headline value is FP64 DoF/s; the FP32 apply and, when requested, the
-mixed-precision solve latency of the manufactured-solution Poisson problem
-are reported beside it.
+headline value is FP64 DoF/s; beside it: the FP32 apply, per-launch
+median/min with warm and flushed caches, the 64^3 affine/curved comparison,
+the mixed-precision and FP64 solve latencies of the manufactured-solution
+Poisson problem, the continuous-batching serving trace, and the oracle on
+the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--solve-reps R] [--only f64|f32] [--copy-calibration MB]
+                       [--no-variants] [--solve-reps R] [--serve-requests R]
+                       [--only f64|f32] [--copy-calibration MB]
 """
 from __future__ import annotations
 
@@ -30,14 +33,20 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1711_03590_amd", "csrc", "kernels.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sipg_apply_f64_curved_k4_32cubed_traffic.txt")
 
 
-def algorithmic_bytes_per_dof(ncell, k, real_bytes):
-    """src read + dst write + every stored geometry value read once:
-    10 per cell quadrature point (J^{-T}, c det J w), 4 per face quadrature
-    point (n.J^{-1}, c ds); neighbour re-reads and tables not counted."""
+GEOMETRY_VALUES = {"curved": (10, 4), "affine-variable": (1, 1), "affine": (0, 0)}
+
+
+def algorithmic_bytes_per_dof(ncell, k, real_bytes, geometry="curved"):
+    """src read + dst write + every stored geometry value read once.  Curved
+    (G3): 10 per cell quadrature point (J^{-T}, c det J w) and 4 per face
+    quadrature point (n.J^{-1}, c ds); affine with a variable coefficient:
+    c det J w per cell point and c ds per face point; affine with a constant
+    coefficient: nothing.  Neighbour re-reads and tables are not counted."""
     n = k + 1
     cells = ncell ** 3
     faces = 3 * ncell * ncell * (ncell + 1)
-    vals = 2 * cells * n ** 3 + 10 * cells * n ** 3 + 4 * faces * n * n
+    cv, fv = GEOMETRY_VALUES[geometry]
+    vals = 2 * cells * n ** 3 + cv * cells * n ** 3 + fv * faces * n * n
     return vals * real_bytes / (cells * n ** 3)
 
 
@@ -71,6 +80,42 @@ def time_apply(op, x, y, steps, warmup, torch):
     end.record()
     torch.cuda.synchronize()
     return start.elapsed_time(end) / steps
+
+
+def measure_hbm(torch, gib=2, reps=10):
+    """Practical HBM rates on this GPU: a read-only pass (sum) and a copy over
+    arrays of gib GiB, far beyond the 256 MB last-level cache."""
+    n = gib * (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    out = {}
+    for name, fn, nbytes in (("read", lambda: a.sum(), n * 8), ("copy", lambda: b.copy_(a), 2 * n * 8)):
+        fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        out[f"{name}_gbs"] = nbytes / (s.elapsed_time(e) / reps * 1e-3) / 1e9
+    del a, b
+    return out
+
+
+def time_apply_each(op, x, y, reps, torch, flush=None):
+    """Per-launch times (ms) of reps individually bracketed applies; with
+    flush, a write of that tensor precedes every launch so that nothing of
+    the operands is left in the 256 MB last-level cache (cold state)."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        if flush is not None:
+            flush.fill_(1.0)
+        a.record()
+        op.apply(x, y)
+        b.record()
+    torch.cuda.synchronize()
+    return sorted(a.elapsed_time(b) for a, b in ev)
 
 
 def cpu_baseline(ncell, k, budget_s=12.0):
@@ -107,12 +152,16 @@ def main():
     ap.add_argument("--degree", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["f64", "f32"], default=None)
-    ap.add_argument("--solve-reps", type=int, default=3,
+    ap.add_argument("--no-variants", dest="variants", action="store_false",
+                    help="skip the 64^3 affine/curved comparison")
+    ap.add_argument("--solve-reps", type=int, default=20,
                     help="repeated config-4 solves per mode for the latency percentiles (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests in the serving trace (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-budget-gib", type=float, default=128.0, help="HBM admission budget")
+    ap.add_argument("--serve-low-rate", type=float, default=10.0,
+                    help="arrival rate of a second, lighter trace (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -133,6 +182,7 @@ def main():
     nd = op.n_dofs
     src = synth.src_vector(nd, synth.seed_for(2, k))
     res = {}
+    flush = torch.empty(512 * (1 << 20) // 4, dtype=torch.float32, device="cuda")
     for prec in ("f64", "f32"):
         if args.only and prec != args.only:
             continue
@@ -143,9 +193,19 @@ def main():
         bpd = algorithmic_bytes_per_dof(N, k, 8 if prec == "f64" else 4)
         achieved = bpd * nd / (ms * 1e-3) / 1e9
         traffic = measured_traffic(prec)
+        warm = time_apply_each(op, x, y, 50, torch)
+        cold = time_apply_each(op, x, y, 20, torch, flush=flush)
         res[prec] = dict(ms=ms, dofs=nd / (ms * 1e-3), bytes_per_dof=bpd, achieved_gbs=achieved,
-                         frac=achieved / HBM_PEAK_GBS, traffic=traffic)
+                         frac=achieved / HBM_PEAK_GBS, traffic=traffic,
+                         per_launch_us={"median": 1e3 * warm[len(warm) // 2], "min": 1e3 * warm[0],
+                                        "cold_median": 1e3 * cold[len(cold) // 2], "cold_min": 1e3 * cold[0]})
         del x, y
+
+    del flush
+    hbm = measure_hbm(torch)
+    variants = None
+    if args.variants:
+        variants = bench_variants(dg, torch, synth, k)
 
     if args.copy_calibration:
         nel = args.copy_calibration * (1 << 20) // 8
@@ -162,6 +222,9 @@ def main():
     serving = None
     if args.serve_requests > 0:
         serving = bench_serve(synth, args.serve_requests, args.serve_rate, args.serve_budget_gib)
+        if args.serve_low_rate > 0:
+            serving["below_capacity"] = bench_serve(synth, max(20, args.serve_requests // 2), args.serve_low_rate,
+                                                    args.serve_budget_gib)
 
     head = res.get("f64") or res.get("f32")
     headp = "f64" if "f64" in res else "f32"
@@ -187,11 +250,15 @@ def main():
                      "algorithmic_bytes_per_dof": head["bytes_per_dof"],
                      "kernel": f"sipg_apply_kernel<{k + 1}, {'double' if headp == 'f64' else 'float'}, CURVED>"},
     }
+    line["per_launch_us"] = head["per_launch_us"]
+    line["hbm_measured"] = dict(hbm, frac_of_read=head["achieved_gbs"] / hbm["read_gbs"])
     if "f32" in res and headp == "f64":
         r = res["f32"]
         line["fp32"] = {"value": r["dofs"], "ms_per_step": r["ms"], "achieved_gbs": r["achieved_gbs"],
                         "frac": r["frac"], "traffic": r["traffic"], "algorithmic_bytes_per_dof": r["bytes_per_dof"],
-                        "speedup_vs_fp64": r["dofs"] / head["dofs"]}
+                        "per_launch_us": r["per_launch_us"], "speedup_vs_fp64": r["dofs"] / head["dofs"]}
+    if variants:
+        line["geometry_variants"] = variants
     if solve:
         line["solve"] = solve
     if serving:
@@ -200,6 +267,32 @@ def main():
         line["cpu_baseline"] = cpu_baseline(N, k)
     print(json.dumps(line), flush=True)
     op.close()
+
+
+def bench_variants(dg, torch, synth, k, ncell=64, steps=30):
+    """64^3 cells, degree k: affine mesh with the variable coefficient (one
+    stored value per cell and face point) against the sine-curved mesh (G3),
+    FP64 and FP32, to compare the traffic of affine and general geometry."""
+    out = {}
+    for name, curved, var in (("affine-variable", False, True), ("curved", True, False)):
+        op = dg.Operator(ncell, k, curved=curved, variable_coef=var, amplitude=synth.AMPLITUDE)
+        nd = op.n_dofs
+        src = synth.src_vector(nd, synth.seed_for(3, k))
+        rec = {"n_dofs": nd}
+        for prec in ("f64", "f32"):
+            dt = torch.float64 if prec == "f64" else torch.float32
+            x = torch.from_numpy(src).to(dtype=dt, device="cuda")
+            y = torch.empty_like(x)
+            ms = time_apply(op, x, y, steps, 3, torch)
+            bpd = algorithmic_bytes_per_dof(ncell, k, 8 if prec == "f64" else 4, name)
+            gbs = bpd * nd / (ms * 1e-3) / 1e9
+            rec[prec] = {"dofs_per_s": nd / (ms * 1e-3), "us": ms * 1e3, "algorithmic_bytes_per_dof": bpd,
+                         "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+            del x, y
+        op.close()
+        out[name] = rec
+    out["workload"] = f"{ncell}^3 cells, k={k}, affine with c = 1 + 0.5 sin(pi x) cos(pi y) z vs sine-curved (G3)"
+    return out
 
 
 def bench_solve(dg, torch, np, synth, reps):
