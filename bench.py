@@ -33,7 +33,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1711_03590_amd", "csrc", "kernels.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sipg_apply_f64_curved_k4_32cubed_traffic.txt")
 
 
-GEOMETRY_VALUES = {"curved": (10, 4), "affine-variable": (1, 1), "affine": (0, 0)}
+GEOMETRY_VALUES = {"curved": (10, 4), "curved-merged": (6, 4), "affine-variable": (1, 1), "affine": (0, 0)}
 
 
 def algorithmic_bytes_per_dof(ncell, k, real_bytes, geometry="curved"):
@@ -41,7 +41,9 @@ def algorithmic_bytes_per_dof(ncell, k, real_bytes, geometry="curved"):
     (G3): 10 per cell quadrature point (J^{-T}, c det J w) and 4 per face
     quadrature point (n.J^{-1}, c ds); affine with a variable coefficient:
     c det J w per cell point and c ds per face point; affine with a constant
-    coefficient: nothing.  Neighbour re-reads and tables are not counted."""
+    coefficient: nothing.  Merged curved storage (G4): the 6 entries of the
+    symmetric c det J w J^{-1} J^{-T} per cell point, faces as G3.  Neighbour
+    re-reads and tables are not counted."""
     n = k + 1
     cells = ncell ** 3
     faces = 3 * ncell * ncell * (ncell + 1)
@@ -203,8 +205,9 @@ def main():
 
     del flush
     hbm = measure_hbm(torch)
-    variants = None
+    variants = merged = None
     if args.variants:
+        merged = bench_merged(dg, torch, synth, N, k, args.steps, args.warmup, res)
         variants = bench_variants(dg, torch, synth, k)
 
     if args.copy_calibration:
@@ -257,6 +260,8 @@ def main():
         line["fp32"] = {"value": r["dofs"], "ms_per_step": r["ms"], "achieved_gbs": r["achieved_gbs"],
                         "frac": r["frac"], "traffic": r["traffic"], "algorithmic_bytes_per_dof": r["bytes_per_dof"],
                         "per_launch_us": r["per_launch_us"], "speedup_vs_fp64": r["dofs"] / head["dofs"]}
+    if merged:
+        line["merged_geometry"] = merged
     if variants:
         line["geometry_variants"] = variants
     if solve:
@@ -271,11 +276,14 @@ def main():
 
 def bench_variants(dg, torch, synth, k, ncell=64, steps=30):
     """64^3 cells, degree k: affine mesh with the variable coefficient (one
-    stored value per cell and face point) against the sine-curved mesh (G3),
-    FP64 and FP32, to compare the traffic of affine and general geometry."""
+    stored value per cell and face point) against the sine-curved mesh with
+    stored Jacobians (G3) and with the merged coefficient (G4), FP64 and
+    FP32, to compare the traffic of affine and general geometry."""
     out = {}
-    for name, curved, var in (("affine-variable", False, True), ("curved", True, False)):
-        op = dg.Operator(ncell, k, curved=curved, variable_coef=var, amplitude=synth.AMPLITUDE)
+    for name, curved, var in (("affine-variable", False, True), ("curved", True, False),
+                              ("curved-merged", True, False)):
+        op = dg.Operator(ncell, k, curved=curved, variable_coef=var, amplitude=synth.AMPLITUDE,
+                         merged=name == "curved-merged")
         nd = op.n_dofs
         src = synth.src_vector(nd, synth.seed_for(3, k))
         rec = {"n_dofs": nd}
@@ -291,7 +299,31 @@ def bench_variants(dg, torch, synth, k, ncell=64, steps=30):
             del x, y
         op.close()
         out[name] = rec
-    out["workload"] = f"{ncell}^3 cells, k={k}, affine with c = 1 + 0.5 sin(pi x) cos(pi y) z vs sine-curved (G3)"
+    out["workload"] = (f"{ncell}^3 cells, k={k}, affine with c = 1 + 0.5 sin(pi x) cos(pi y) z vs sine-curved, "
+                       "stored Jacobians (G3) and merged coefficient (G4)")
+    return out
+
+
+def bench_merged(dg, torch, synth, ncell, k, steps, warmup, g3):
+    """The headline workload with the merged cell geometry (G4): same
+    operator up to rounding, 6 instead of 10 values per cell point."""
+    op = dg.Operator(ncell, k, curved=True, amplitude=synth.AMPLITUDE, merged=True)
+    nd = op.n_dofs
+    src = synth.src_vector(nd, synth.seed_for(2, k))
+    out = {"workload": f"{ncell}^3 sine-curved, k={k}, merged cell geometry (G4)"}
+    for prec in ("f64", "f32"):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        x = torch.from_numpy(src).to(dtype=dt, device="cuda")
+        y = torch.empty_like(x)
+        ms = time_apply(op, x, y, steps, warmup, torch)
+        bpd = algorithmic_bytes_per_dof(ncell, k, 8 if prec == "f64" else 4, "curved-merged")
+        gbs = bpd * nd / (ms * 1e-3) / 1e9
+        out[prec] = {"dofs_per_s": nd / (ms * 1e-3), "us": ms * 1e3, "algorithmic_bytes_per_dof": bpd,
+                     "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+        if prec in g3:
+            out[prec]["speedup_vs_g3"] = out[prec]["dofs_per_s"] / g3[prec]["dofs"]
+        del x, y
+    op.close()
     return out
 
 

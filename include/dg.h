@@ -72,9 +72,17 @@ typedef struct {
  * Design Choice 5).  DG_MAP_AFFINE stores no geometry per point (the
  * constant-Jacobian compression of Sec. 5). */
 typedef enum { DG_MAP_AFFINE = 0, DG_MAP_SINE = 1 } dg_map;
+/* What a curved map stores per cell quadrature point (Sec. 5):
+ * DG_STORE_JACOBIAN  the inverse Jacobian and c det J w, 10 values (G3);
+ * DG_STORE_MERGED    the symmetric effective coefficient
+ *                    c det J w J^{-1} J^{-T} of the Laplacian, 6 values (G4).
+ * Both give the same operator up to rounding; faces store j = J^{-1} n and
+ * c ds either way.  Ignored for DG_MAP_AFFINE. */
+typedef enum { DG_STORE_JACOBIAN = 0, DG_STORE_MERGED = 1 } dg_storage;
 typedef struct {
   dg_map map;
   double amplitude;
+  dg_storage storage;
 } dg_geometry;
 
 /* DG_COEF_CONST: c = value.  DG_COEF_SINCOS: c = 1 + 0.5 sin(pi x) cos(pi y) z

@@ -18,6 +18,7 @@ DG_OK, DG_ERR_ARG, DG_ERR_OOM, DG_ERR_HIP, DG_ERR_UNSUPPORTED, DG_ERR_NOT_CONVER
 F64, F32 = 0, 1
 DIRICHLET, NEUMANN = 0, 1
 MAP_AFFINE, MAP_SINE = 0, 1
+STORE_JACOBIAN, STORE_MERGED = 0, 1
 COEF_CONST, COEF_SINCOS = 0, 1
 PREC_F64, PREC_F32 = 1, 2
 
@@ -34,7 +35,7 @@ class Mesh(ctypes.Structure):
 
 
 class Geometry(ctypes.Structure):
-    _fields_ = [("map", ctypes.c_int), ("amplitude", ctypes.c_double)]
+    _fields_ = [("map", ctypes.c_int), ("amplitude", ctypes.c_double), ("storage", ctypes.c_int)]
 
 
 class Coefficient(ctypes.Structure):
@@ -142,9 +143,9 @@ def make_mesh(ncell, bc=(DIRICHLET,) * 6, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)
 
 
 def footprint(ncell, degree, *, curved=False, amplitude=0.05, variable_coef=False, coef_value=1.0,
-              precisions=PREC_F64 | PREC_F32, bc=(DIRICHLET,) * 6):
+              precisions=PREC_F64 | PREC_F32, bc=(DIRICHLET,) * 6, merged=False):
     m = make_mesh(ncell, bc)
-    g = Geometry(MAP_SINE if curved else MAP_AFFINE, amplitude)
+    g = Geometry(MAP_SINE if curved else MAP_AFFINE, amplitude, STORE_MERGED if merged else STORE_JACOBIAN)
     c = Coefficient(COEF_SINCOS if variable_coef else COEF_CONST, coef_value)
     out = ctypes.c_size_t()
     check(lib().dg_footprint(ctypes.byref(m), degree, ctypes.byref(g), ctypes.byref(c), precisions,
@@ -203,16 +204,17 @@ class Operator:
 
     def __init__(self, ncell, degree, *, curved=False, amplitude=0.05, variable_coef=False, coef_value=1.0,
                  bc=(DIRICHLET,) * 6, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
-                 precisions=PREC_F64 | PREC_F32, torch_alloc=True, stream=None):
+                 precisions=PREC_F64 | PREC_F32, torch_alloc=True, stream=None, merged=False):
         self._h = None
         self.degree = degree
         self.mesh = make_mesh(ncell, bc, lo, hi)
         self.ncell = tuple(self.mesh.ncell)
         self.curved = curved
+        self.merged = merged and curved
         self.variable_coef = variable_coef
         self.precisions = precisions
         self._alloc = TorchAllocator() if torch_alloc else None
-        g = Geometry(MAP_SINE if curved else MAP_AFFINE, amplitude)
+        g = Geometry(MAP_SINE if curved else MAP_AFFINE, amplitude, STORE_MERGED if merged else STORE_JACOBIAN)
         c = Coefficient(COEF_SINCOS if variable_coef else COEF_CONST, coef_value)
         h = ctypes.c_void_p()
         check(lib().dg_setup(ctypes.byref(self.mesh), degree, ctypes.byref(g), ctypes.byref(c), precisions,

@@ -16,7 +16,15 @@ namespace dgk {
 //   AFFINE_VAR    constant Jacobian, c * det J * w per cell point, c * ds per face point
 //   CURVED        G3: J^{-T} (9) and c * det J * w per cell point;
 //                 face: j = J^{-1} n (3, Design Choice 5) and c * ds per face point
-enum GeomKind : int { AFFINE_CONST = 0, AFFINE_VAR = 1, CURVED = 2 };
+//   CURVED_MERGED G4: the symmetric c * det J * w * J^{-1} J^{-T} (6) per cell
+//                 point; faces as CURVED
+enum GeomKind : int { AFFINE_CONST = 0, AFFINE_VAR = 1, CURVED = 2, CURVED_MERGED = 3 };
+
+// faces carry j = J^{-1} n and c ds per point
+constexpr bool curved_faces(int gk) { return gk == CURVED || gk == CURVED_MERGED; }
+// stored values per cell quadrature point
+constexpr int cell_values(int gk) { return gk == CURVED ? 10 : (gk == CURVED_MERGED ? 6 : (gk == AFFINE_VAR ? 1 : 0)); }
+constexpr int face_values(int gk) { return curved_faces(gk) ? 4 : (gk == AFFINE_VAR ? 1 : 0); }
 
 constexpr int kMinN = 2;  // degree 1
 constexpr int kMaxN = 9;  // degree 8
@@ -28,8 +36,9 @@ constexpr int kMaxN = 9;  // degree 8
 // ncell[a] + 1 planes in that direction.
 template <typename Real>
 struct GeomData {
-  const Real *cell = nullptr;          // CURVED: 10 arrays (J^{-T} row-major, then cJxW); AFFINE_VAR: 1 (cJxW)
-  const Real *face[3] = {nullptr, nullptr, nullptr};  // CURVED: 4 arrays (j0, j1, j2, cds); AFFINE_VAR: 1 (cds)
+  const Real *cell = nullptr;          // CURVED: 10 arrays (J^{-T} row-major, then cJxW);
+                                       // CURVED_MERGED: 6 (M00, M01, M02, M11, M12, M22); AFFINE_VAR: 1 (cJxW)
+  const Real *face[3] = {nullptr, nullptr, nullptr};  // curved: 4 arrays (j0, j1, j2, cds); AFFINE_VAR: 1 (cds)
   int64_t cell_stride = 0;             // elements between successive quantity arrays
   int64_t face_stride[3] = {0, 0, 0};
 };

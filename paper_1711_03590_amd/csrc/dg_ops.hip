@@ -194,6 +194,17 @@ __global__ void geom_cells_kernel(const GeoArgs g, int64_t npts, double *o64, fl
       }
     if (o64) o64[9 * stride + idx] = cjxw;
     if (o32) o32[9 * stride + idx] = (float)cjxw;
+  } else if (GK == CURVED_MERGED) {
+    // M = c det J w J^{-1} J^{-T}: M[b][c] = cjxw sum_a J^{-T}[a][b] J^{-T}[a][c]
+    double jt[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) jt[a][b] = Gi[b][a] / g.h[b];
+    const int rb[6] = {0, 0, 0, 1, 1, 2}, rc[6] = {0, 1, 2, 1, 2, 2};
+    for (int e = 0; e < 6; ++e) {
+      const double v = cjxw * (jt[0][rb[e]] * jt[0][rc[e]] + jt[1][rb[e]] * jt[1][rc[e]] + jt[2][rb[e]] * jt[2][rc[e]]);
+      if (o64) o64[e * stride + idx] = v;
+      if (o32) o32[e * stride + idx] = (float)v;
+    }
   } else {
     if (o64) o64[idx] = cjxw;
     if (o32) o32[idx] = (float)cjxw;
@@ -391,8 +402,14 @@ static GeoArgs geo_args(const dg_op *op)
   return g;
 }
 
-static int64_t geom_cell_values(int gk) { return gk == CURVED ? 10 : (gk == AFFINE_VAR ? 1 : 0); }
-static int64_t geom_face_values(int gk) { return gk == CURVED ? 4 : (gk == AFFINE_VAR ? 1 : 0); }
+static int64_t geom_cell_values(int gk) { return cell_values(gk); }
+static int64_t geom_face_values(int gk) { return face_values(gk); }
+
+static int geom_kind(const dg_geometry *geom, const dg_coefficient *coef)
+{
+  if (geom->map == DG_MAP_SINE) return geom->storage == DG_STORE_MERGED ? CURVED_MERGED : CURVED;
+  return coef->kind == DG_COEF_SINCOS ? AFFINE_VAR : AFFINE_CONST;
+}
 
 static size_t footprint_bytes(const int64_t nc[3], int n, int gk, unsigned prec)
 {
@@ -424,6 +441,8 @@ static dg_status validate(const dg_mesh *mesh, int degree, const dg_geometry *ge
   for (int f = 0; f < 6; ++f)
     if (mesh->bc[f] != DG_BC_DIRICHLET && mesh->bc[f] != DG_BC_NEUMANN) return fail(DG_ERR_ARG, "bad bc");
   if (geom->map != DG_MAP_AFFINE && geom->map != DG_MAP_SINE) return fail(DG_ERR_ARG, "bad map");
+  if (geom->storage != DG_STORE_JACOBIAN && geom->storage != DG_STORE_MERGED)
+    return fail(DG_ERR_ARG, "bad geometry storage");
   if (coef->kind != DG_COEF_CONST && coef->kind != DG_COEF_SINCOS) return fail(DG_ERR_ARG, "bad coefficient");
   if (precisions == 0 || (precisions & ~3u)) return fail(DG_ERR_ARG, "precisions must be a nonempty subset of F64|F32");
   const int64_t n = degree + 1;
@@ -473,7 +492,7 @@ dg_status dg_footprint(const dg_mesh *mesh, int degree, const dg_geometry *geom,
   dg_status st = validate(mesh, degree, geom, coef, precisions);
   if (st != DG_OK) return st;
   if (!bytes) return fail(DG_ERR_ARG, "bytes is null");
-  const int gk = geom->map == DG_MAP_SINE ? CURVED : (coef->kind == DG_COEF_SINCOS ? AFFINE_VAR : AFFINE_CONST);
+  const int gk = geom_kind(geom, coef);
   const int64_t nc[3] = {mesh->ncell[0], mesh->ncell[1], mesh->ncell[2]};
   *bytes = footprint_bytes(nc, degree + 1, gk, precisions);
   return DG_OK;
@@ -509,7 +528,7 @@ dg_status dg_setup(const dg_mesh *mesh, int degree, const dg_geometry *geom, con
   op->geom = *geom;
   op->coef = *coef;
   op->precisions = precisions;
-  op->gk = geom->map == DG_MAP_SINE ? CURVED : (coef->kind == DG_COEF_SINCOS ? AFFINE_VAR : AFFINE_CONST);
+  op->gk = geom_kind(geom, coef);
   if (alloc) {
     op->alloc = *alloc;
     op->own_alloc = false;
@@ -565,6 +584,8 @@ dg_status dg_setup(const dg_mesh *mesh, int degree, const dg_geometry *geom, con
     double *o64 = static_cast<double *>(op->cell_geo[0]);
     float *o32 = static_cast<float *>(op->cell_geo[1]);
     if (op->gk == CURVED) hipLaunchKernelGGL(geom_cells_kernel<CURVED>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
+    else if (op->gk == CURVED_MERGED)
+      hipLaunchKernelGGL(geom_cells_kernel<CURVED_MERGED>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
     else hipLaunchKernelGGL(geom_cells_kernel<AFFINE_VAR>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cleanup(hip_fail(e, "geometry kernel"));
@@ -575,7 +596,7 @@ dg_status dg_setup(const dg_mesh *mesh, int degree, const dg_geometry *geom, con
       const int grid = (int)((npts + 255) / 256);
       double *o64 = static_cast<double *>(op->face_geo[0][a]);
       float *o32 = static_cast<float *>(op->face_geo[1][a]);
-      if (op->gk == CURVED) hipLaunchKernelGGL(geom_faces_kernel<CURVED>, dim3(grid), dim3(256), 0, s, g, a, npts, o64, o32, npts);
+      if (curved_faces(op->gk)) hipLaunchKernelGGL(geom_faces_kernel<CURVED>, dim3(grid), dim3(256), 0, s, g, a, npts, o64, o32, npts);
       else hipLaunchKernelGGL(geom_faces_kernel<AFFINE_VAR>, dim3(grid), dim3(256), 0, s, g, a, npts, o64, o32, npts);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return cleanup(hip_fail(e, "face geometry kernel"));

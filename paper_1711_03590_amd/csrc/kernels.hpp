@@ -244,7 +244,7 @@ __device__ __forceinline__ void face_geometry(const OpView<Real> &op, const int 
   constexpr int N2 = N * N;
   constexpr Tables<N> T = kTab<N>;
   j[0] = j[1] = j[2] = Real(0);
-  if constexpr (GK == CURVED) {
+  if constexpr (curved_faces(GK)) {
     const int64_t f = face_id<A>(op.ncell, ci, s) * N2 + l;
     const Real *fg = op.g.face[A];
     const int64_t fs = op.g.face_stride[A];
@@ -539,13 +539,14 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
   // (c) face terms, direction by direction, into R; the stored cell geometry
   // of the first planes is requested during the last direction
   constexpr int NB = (DG_GEO_BUFS < N) ? DG_GEO_BUFS : N;
-  Real gbuf[NB][10];
-  auto load_geometry = [&](int k, Real (&gb)[10]) {
-    if constexpr (GK == CURVED) {
+  constexpr int GV = (GK == CURVED || GK == CURVED_MERGED) ? cell_values(GK) : 1;
+  Real gbuf[NB][GV];
+  auto load_geometry = [&](int k, Real (&gb)[GV]) {
+    if constexpr (GK == CURVED || GK == CURVED_MERGED) {
       const int64_t ix = (int64_t)cell * N3 + l + k * N2;
       const int64_t cs = op.g.cell_stride;
 #pragma unroll
-      for (int m = 0; m < 10; ++m) gb[m] = op.g.cell[m * cs + ix];
+      for (int m = 0; m < GV; ++m) gb[m] = op.g.cell[m * cs + ix];
     }
   };
   face_direction<N, Real, GK, 0>(op, Q, R, W, l, ci, act, valid, nb,
@@ -587,6 +588,14 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
         for (int a = 0; a < 3; ++a) gx[a] = f * (jt[3 * a] * g[0] + jt[3 * a + 1] * g[1] + jt[3 * a + 2] * g[2]);
 #pragma unroll
         for (int b = 0; b < 3; ++b) o[b] = jt[b] * gx[0] + jt[3 + b] * gx[1] + jt[6 + b] * gx[2];
+        __builtin_amdgcn_sched_barrier(0);
+        if (k + NB < N) load_geometry(k + NB, gbuf[k % NB]);
+      } else if constexpr (GK == CURVED_MERGED) {
+        // G4: t = M grad_xi u with the symmetric M = c det J w J^{-1} J^{-T}
+        const Real *M = gbuf[k % NB];
+        o[0] = M[0] * g[0] + M[1] * g[1] + M[2] * g[2];
+        o[1] = M[1] * g[0] + M[3] * g[1] + M[4] * g[2];
+        o[2] = M[2] * g[0] + M[4] * g[1] + M[5] * g[2];
         __builtin_amdgcn_sched_barrier(0);
         if (k + NB < N) load_geometry(k + NB, gbuf[k % NB]);
       } else {
@@ -674,13 +683,13 @@ sipg_diag_kernel(const OpView<double> op, double *__restrict__ d64, float *__res
 {
   constexpr int N2 = N * N, N3 = N2 * N;
   constexpr Tables<N> T = kTab<N>;
-  constexpr int NG = (GK == CURVED) ? 10 : 1;
+  constexpr int NG = (GK == CURVED || GK == CURVED_MERGED) ? cell_values(GK) : 1;
   __shared__ double geo[NG * N3];
   const int cell = blockIdx.x;
   const int i = threadIdx.x;
   for (int m = i; m < NG * N3; m += blockDim.x) {
     const int q = m % N3, f = m / N3;
-    if constexpr (GK == CURVED) geo[m] = op.g.cell[f * op.g.cell_stride + (int64_t)cell * N3 + q];
+    if constexpr (GK == CURVED || GK == CURVED_MERGED) geo[m] = op.g.cell[f * op.g.cell_stride + (int64_t)cell * N3 + q];
     else if constexpr (GK == AFFINE_VAR) geo[m] = op.g.cell[(int64_t)cell * N3 + q];
     else geo[m] = op.c_vol * T.gw[q % N] * T.gw[(q / N) % N] * T.gw[q / N2];
   }
@@ -716,6 +725,9 @@ sipg_diag_kernel(const OpView<double> op, double *__restrict__ d64, float *__res
             s2 += gx * gx;
           }
           acc += geo[9 * N3 + q] * s2;
+        } else if constexpr (GK == CURVED_MERGED) {
+          acc += geo[q] * g[0] * g[0] + geo[3 * N3 + q] * g[1] * g[1] + geo[5 * N3 + q] * g[2] * g[2] +
+                 2.0 * (geo[N3 + q] * g[0] * g[1] + geo[2 * N3 + q] * g[0] * g[2] + geo[4 * N3 + q] * g[1] * g[2]);
         } else {
           acc += geo[q] * (op.inv_h[0] * op.inv_h[0] * g[0] * g[0] + op.inv_h[1] * op.inv_h[1] * g[1] * g[1] +
                            op.inv_h[2] * op.inv_h[2] * g[2] * g[2]);
@@ -752,7 +764,7 @@ sipg_diag_kernel(const OpView<double> op, double *__restrict__ d64, float *__res
           g[t1] = Dc[t1][q1] * Sc[t2][q2];
           g[t2] = Sc[t1][q1] * Dc[t2][q2];
           double j[3] = {0.0, 0.0, 0.0}, cds;
-          if constexpr (GK == CURVED) {
+          if constexpr (curved_faces(GK)) {
             const double *fg = op.g.face[a];
             const int64_t fs = op.g.face_stride[a], f = fid * N2 + lq;
             j[0] = fg[f];
@@ -787,6 +799,7 @@ hipError_t launch_apply(const dg_op *op, const void *src, void *dst, bool f32, h
     float *y = static_cast<float *>(dst);
     switch (op->gk) {
       case CURVED: hipLaunchKernelGGL((sipg_apply_kernel<N, float, CURVED>), dim3(grid), dim3(BK::TPB), 0, s, op->v32, x, y); break;
+      case CURVED_MERGED: hipLaunchKernelGGL((sipg_apply_kernel<N, float, CURVED_MERGED>), dim3(grid), dim3(BK::TPB), 0, s, op->v32, x, y); break;
       case AFFINE_VAR: hipLaunchKernelGGL((sipg_apply_kernel<N, float, AFFINE_VAR>), dim3(grid), dim3(BK::TPB), 0, s, op->v32, x, y); break;
       default: hipLaunchKernelGGL((sipg_apply_kernel<N, float, AFFINE_CONST>), dim3(grid), dim3(BK::TPB), 0, s, op->v32, x, y); break;
     }
@@ -795,6 +808,7 @@ hipError_t launch_apply(const dg_op *op, const void *src, void *dst, bool f32, h
     double *y = static_cast<double *>(dst);
     switch (op->gk) {
       case CURVED: hipLaunchKernelGGL((sipg_apply_kernel<N, double, CURVED>), dim3(grid), dim3(BK::TPB), 0, s, op->v64, x, y); break;
+      case CURVED_MERGED: hipLaunchKernelGGL((sipg_apply_kernel<N, double, CURVED_MERGED>), dim3(grid), dim3(BK::TPB), 0, s, op->v64, x, y); break;
       case AFFINE_VAR: hipLaunchKernelGGL((sipg_apply_kernel<N, double, AFFINE_VAR>), dim3(grid), dim3(BK::TPB), 0, s, op->v64, x, y); break;
       default: hipLaunchKernelGGL((sipg_apply_kernel<N, double, AFFINE_CONST>), dim3(grid), dim3(BK::TPB), 0, s, op->v64, x, y); break;
     }
@@ -813,6 +827,7 @@ hipError_t launch_diag(const dg_op *op, void *diag64, void *diag32, hipStream_t 
   float *d32 = static_cast<float *>(diag32);
   switch (op->gk) {
     case CURVED: hipLaunchKernelGGL((sipg_diag_kernel<N, CURVED>), dim3(grid), dim3(block), 0, s, op->v64, d64, d32); break;
+    case CURVED_MERGED: hipLaunchKernelGGL((sipg_diag_kernel<N, CURVED_MERGED>), dim3(grid), dim3(block), 0, s, op->v64, d64, d32); break;
     case AFFINE_VAR: hipLaunchKernelGGL((sipg_diag_kernel<N, AFFINE_VAR>), dim3(grid), dim3(block), 0, s, op->v64, d64, d32); break;
     default: hipLaunchKernelGGL((sipg_diag_kernel<N, AFFINE_CONST>), dim3(grid), dim3(block), 0, s, op->v64, d64, d32); break;
   }

@@ -11,7 +11,8 @@ pytestmark = pytest.mark.gpu
 REQS = [((6, 5, 4), 2, dict(curved=True)),
         ((4, 4, 4), 5, dict(curved=False)),
         ((3, 4, 5), 3, dict(curved=True, variable_coef=True)),
-        ((5, 3, 3), 7, dict(curved=True))]
+        ((5, 3, 3), 7, dict(curved=True)),
+        ((4, 5, 3), 4, dict(curved=True, merged=True))]
 
 
 @pytest.fixture(scope="module")

@@ -85,3 +85,25 @@ def test_footprint_counts(dg):
     assert dg.footprint(N, k, precisions=dg.PREC_F64 | dg.PREC_F32) == cells * n ** 3 * 12
     assert dg.footprint(N, k, variable_coef=True, precisions=dg.PREC_F32) == \
         (cells * n ** 3 + faces * n ** 2) * 4 + cells * n ** 3 * 4
+
+
+def test_footprint_merged_geometry(dg):
+    # merged (G4): 6 values per cell point instead of 10; faces unchanged
+    k, N = 4, 32
+    n = k + 1
+    cells = N ** 3
+    full = dg.footprint(N, k, curved=True)
+    merged = dg.footprint(N, k, curved=True, merged=True)
+    assert full - merged == 4 * cells * n ** 3 * (8 + 4)
+    # the storage choice does not apply to affine maps
+    assert dg.footprint(N, k, merged=True) == dg.footprint(N, k)
+
+
+def test_bad_storage_rejected(dg):
+    import ctypes
+    m = dg.make_mesh(4, (dg.DIRICHLET,) * 6)
+    g = dg.Geometry(dg.MAP_SINE, 0.05, 7)
+    c = dg.Coefficient(0, 1.0)
+    out = ctypes.c_size_t()
+    st = dg.lib().dg_footprint(ctypes.byref(m), 3, ctypes.byref(g), ctypes.byref(c), dg.PREC_F64, ctypes.byref(out))
+    assert st == dg.DG_ERR_ARG
