@@ -305,6 +305,20 @@ __device__ __forceinline__ void load_neighbour_lines(const OpView<Real> &op, con
   }
 }
 
+// Jobs jb = 0 .. JOBS-1 of one cell spread over its N^2 lanes (a lane takes
+// several when JOBS > N^2); unrolled, so that the common single pass has no
+// loop around it.
+template <int N, int JOBS, typename F>
+__device__ __forceinline__ void for_jobs(int l, bool act, F &&f)
+{
+  constexpr int N2 = N * N, IT = (JOBS + N2 - 1) / N2;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int jb = l + it * N2;
+    if (act && jb < JOBS) f(jb);
+  }
+}
+
 // Face terms of direction A for this thread group's cell: the face integrals
 // of Sec. 2 Eq. (2) over the cell's two faces normal to A, own side only
 // (the element's share of Algorithm 1 steps (iii)-(iv)), added into the
@@ -363,34 +377,28 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
   // loads for what follows (the next direction's neighbour lines, or the
   // first planes of cell geometry), in flight through the rest of the faces
   next();
-  // S2: neighbour traces, basis change along t1 (one line per job)
-  // (2N jobs; with N^2 < 2N threads per cell a thread takes several)
-  if (act) for (int jb = l; jb < 2 * N; jb += N2) {
-    const int s = jb / N, p2 = jb - s * N;
+  // S2: neighbour traces, basis change along t1: one line of one of the
+  // four arrays [s][value, derivative] per job (4N jobs over the N^2 lanes)
+  for_jobs<N, 4 * N>(l, act, [&](int jb) {
+    const int a = jb / N, p2 = jb - a * N;
     Real v[N], r[N];
 #pragma unroll
-    for (int f = 0; f < 2; ++f) {
+    for (int m = 0; m < N; ++m) v[m] = X[a * N2 + m + N * p2];
+    eo_apply<N, M_S>(v, r);
 #pragma unroll
-      for (int m = 0; m < N; ++m) v[m] = X[(2 * s + f) * N2 + m + N * p2];
-      eo_apply<N, M_S>(v, r);
-#pragma unroll
-      for (int m = 0; m < N; ++m) Y[(2 * s + f) * N2 + m + N * p2] = r[m];
-    }
-  }
+    for (int m = 0; m < N; ++m) Y[a * N2 + m + N * p2] = r[m];
+  });
   __syncthreads();
   // S3: basis change along t2
-  if (act) for (int jb = l; jb < 2 * N; jb += N2) {
-    const int s = jb / N, q1 = jb - s * N;
+  for_jobs<N, 4 * N>(l, act, [&](int jb) {
+    const int a = jb / N, q1 = jb - a * N;
     Real v[N], r[N];
 #pragma unroll
-    for (int f = 0; f < 2; ++f) {
+    for (int m = 0; m < N; ++m) v[m] = Y[a * N2 + q1 + N * m];
+    eo_apply<N, M_S>(v, r);
 #pragma unroll
-      for (int m = 0; m < N; ++m) v[m] = Y[(2 * s + f) * N2 + q1 + N * m];
-      eo_apply<N, M_S>(v, r);
-#pragma unroll
-      for (int m = 0; m < N; ++m) U[(2 * s + f) * N2 + q1 + N * m] = r[m];
-    }
-  }
+    for (int m = 0; m < N; ++m) U[a * N2 + q1 + N * m] = r[m];
+  });
   __syncthreads();
   // S4: jump, sum of values, sum of normal reference derivatives
   Real jump[2] = {Real(0), Real(0)}, dsum[2] = {Real(0), Real(0)};
@@ -412,7 +420,7 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
   }
   __syncthreads();
   // S5: tangential collocation derivatives of V (lines along t1 and t2)
-  if (act) for (int jb = l; jb < 4 * N; jb += N2) {
+  for_jobs<N, 4 * N>(l, act, [&](int jb) {
     const int s = jb / (2 * N), c = (jb / N) & 1, i = jb % N;
     const int base = c ? i : N * i, stride = c ? N : 1;
     Real v[N], r[N];
@@ -421,7 +429,7 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
     eo_apply<N, M_DCO>(v, r);
 #pragma unroll
     for (int m = 0; m < N; ++m) dV[(2 * s + c) * N2 + base + m * stride] = r[m];
-  }
+  });
   __syncthreads();
   // S6: numerical flux at this face point (Algorithm 1 step (c) for faces)
   Real tv[2] = {Real(0), Real(0)}, tga[2] = {Real(0), Real(0)};
@@ -445,7 +453,7 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
   }
   __syncthreads();
   // S7: transposed tangential collocation derivatives of the gradient-test terms
-  if (act) for (int jb = l; jb < 4 * N; jb += N2) {
+  for_jobs<N, 4 * N>(l, act, [&](int jb) {
     const int s = jb / (2 * N), c = (jb / N) & 1, i = jb % N;
     const int base = c ? i : N * i, stride = c ? N : 1;
     Real v[N], r[N];
@@ -454,7 +462,7 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
     eo_apply<N, M_DCOT>(v, r);
 #pragma unroll
     for (int m = 0; m < N; ++m) Z2[(2 * s + c) * N2 + base + m * stride] = r[m];
-  }
+  });
   __syncthreads();
   // S8: face-normal integration onto this thread's normal line of R
   if (act) {
