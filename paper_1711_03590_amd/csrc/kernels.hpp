@@ -330,7 +330,7 @@ __device__ __forceinline__ void for_jobs(int l, bool act, F &&f)
 template <int N, typename Real, int GK, int A, typename Next>
 __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Real *Q, Real *R, Real *W, int l,
                                                const int (&ci)[3], bool act, bool valid, const Real (&nb)[2][N],
-                                               Next &&next)
+                                               Real (&fz)[4], Next &&next)
 {
   constexpr int N2 = N * N;
   constexpr int t1 = (A == 0) ? 1 : 0, t2 = (A == 2) ? 1 : 2;
@@ -464,25 +464,35 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
     for (int m = 0; m < N; ++m) Z2[(2 * s + c) * N2 + base + m * stride] = r[m];
   });
   __syncthreads();
-  // S8: face-normal integration onto this thread's normal line of R
+  // S8: face-normal integration onto this thread's normal line of R: the
+  // rank-4 update L0 w0 + dL0 tga0 + L1 w1 + dL1 tga1.  The first direction
+  // initialises R, the second adds to it, and the third hands its four
+  // coefficients (fz) to the cell pass, which owns the same z-line.  No
+  // barrier follows: the next writer of Z2's storage is two barriers away.
   if (act) {
     Real w[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) w[s] = tv[s] + Z2[(2 * s) * N2 + l] + Z2[(2 * s + 1) * N2 + l];
-    Real r[N];
-    load_line<N, A>(R, l, r);
+    if constexpr (A == 2) {
+      fz[0] = w[0];
+      fz[1] = tga[0];
+      fz[2] = w[1];
+      fz[3] = tga[1];
+    } else {
+      Real r[N];
+      if constexpr (A == 1) load_line<N, A>(R, l, r);
 #pragma unroll
-    for (int m = 0; m < N; ++m) {
-      Real v = r[m];
-      v = madd(T.L0[m], w[0], v);
-      v = fma(Real(T.dL0[m]), tga[0], v);
-      v = madd(T.L1[m], w[1], v);
-      v = fma(Real(T.dL1[m]), tga[1], v);
-      r[m] = v;
+      for (int m = 0; m < N; ++m) {
+        Real v = (A == 1) ? r[m] : Real(-0.0);
+        v = madd(T.L0[m], w[0], v);
+        v = fma(Real(T.dL0[m]), tga[0], v);
+        v = madd(T.L1[m], w[1], v);
+        v = fma(Real(T.dL1[m]), tga[1], v);
+        r[m] = v;
+      }
+      store_line<N, A>(R, l, r);
     }
-    store_line<N, A>(R, l, r);
   }
-  __syncthreads();
 }
 
 // The fused pass over the cells of one batch (cells blk*B .. blk*B+B-1) by
@@ -526,7 +536,7 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
   __builtin_amdgcn_sched_barrier(0);  // keep the gather ahead of the neighbour loads
   Real nb[2][N];
   load_neighbour_lines<N, Real, 0>(op, src, cell, l, ci, nb);
-  // (slots past B N^3 fall into R, which is cleared before it is used)
+  // (slots past B N^3 fall into R, which the first face direction overwrites)
   static_assert(GI * TPB <= 2 * B * N3, "gather overrun");
 #pragma unroll
   for (int j = 0; j < GI; ++j) {
@@ -537,7 +547,6 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
 
   // (b) basis change to the Gauss points (Eq. (6), right factor)
   if (act) sweep<N, 0, M_S>(Q, Q, l);
-  for (int i = t; i < B * N3; i += TPB) smem[B * N3 + i] = Real(0);  // R
   __syncthreads();
   if (act) sweep<N, 1, M_S>(Q, Q, l);
   __syncthreads();
@@ -557,17 +566,19 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
       for (int m = 0; m < GV; ++m) gb[m] = op.g.cell[m * cs + ix];
     }
   };
-  face_direction<N, Real, GK, 0>(op, Q, R, W, l, ci, act, valid, nb,
+  Real fz[4] = {Real(0), Real(0), Real(0), Real(0)};
+  face_direction<N, Real, GK, 0>(op, Q, R, W, l, ci, act, valid, nb, fz,
                                  [&] { load_neighbour_lines<N, Real, 1>(op, src, cell, l, ci, nb); });
-  face_direction<N, Real, GK, 1>(op, Q, R, W, l, ci, act, valid, nb,
+  face_direction<N, Real, GK, 1>(op, Q, R, W, l, ci, act, valid, nb, fz,
                                  [&] { load_neighbour_lines<N, Real, 2>(op, src, cell, l, ci, nb); });
   constexpr int PRE = (DG_GEO_PRE < NB) ? DG_GEO_PRE : NB;
-  face_direction<N, Real, GK, 2>(op, Q, R, W, l, ci, act, valid, nb, [&] {
+  face_direction<N, Real, GK, 2>(op, Q, R, W, l, ci, act, valid, nb, fz, [&] {
 #pragma unroll
     for (int k = 0; k < PRE; ++k) load_geometry(k, gbuf[k]);
   });
 #pragma unroll
   for (int k = PRE; k < NB; ++k) load_geometry(k, gbuf[k]);
+  __syncthreads();  // the z faces' Z2 reads are done before W takes the gradients
 
   // (d) cell integrals: collocation derivatives along x and y (z is taken
   // in registers below), then the quadrature-point operation along this
@@ -630,8 +641,16 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
     Real rz[N], q[N];
     eo_apply<N, M_DCOT>(t2v, rz);
     load_line<N, 2>(R, l, q);
+    // plus the z faces' normal integration onto the same line
 #pragma unroll
-    for (int m = 0; m < N; ++m) q[m] += rz[m];
+    for (int m = 0; m < N; ++m) {
+      Real v = q[m] + rz[m];
+      v = madd(T.L0[m], fz[0], v);
+      v = fma(Real(T.dL0[m]), fz[1], v);
+      v = madd(T.L1[m], fz[2], v);
+      v = fma(Real(T.dL1[m]), fz[3], v);
+      q[m] = v;
+    }
     store_line<N, 2>(R, l, q);
   }
   __syncthreads();
