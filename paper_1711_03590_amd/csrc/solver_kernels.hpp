@@ -39,14 +39,29 @@ __device__ __forceinline__ Acc reduce_partials(const Acc *part, int stride, Acc 
 // The chunk-th piece of a reduction (chunk in [0, kRedBlocks)) covers the
 // elements chunk*T + t + j*kRedBlocks*T; the kernels below run one chunk per
 // workgroup, the batched kernels one chunk of one request per workgroup, so
-// a request's sums do not depend on what else shares the launch.
+// a request's sums do not depend on what else shares the launch.  Each
+// thread takes its elements four at a time (loads first, then the
+// arithmetic in the same order as one at a time), so that enough loads are
+// in flight to keep HBM busy with one workgroup per chunk.
+constexpr int kUnroll = 4;
+constexpr int64_t kChunkStride = (int64_t)kRedBlocks * kRedThreads;
 template <typename Real, typename Acc>
 __device__ __forceinline__ void dot_partial_body(const Real *__restrict__ x, const Real *__restrict__ y, int64_t n,
                                                  Acc *__restrict__ part, int chunk, Acc *sh)
 {
   Acc v = Acc(0);
-  for (int64_t i = (int64_t)chunk * kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads)
-    v += (Acc)x[i] * (Acc)y[i];
+  int64_t i = (int64_t)chunk * kRedThreads + threadIdx.x;
+  for (; i + (kUnroll - 1) * kChunkStride < n; i += kUnroll * kChunkStride) {
+    Real a[kUnroll], b[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      a[u] = x[i + u * kChunkStride];
+      b[u] = y[i + u * kChunkStride];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) v += (Acc)a[u] * (Acc)b[u];
+  }
+  for (; i < n; i += kChunkStride) v += (Acc)x[i] * (Acc)y[i];
   v = block_sum(v, sh);
   if (threadIdx.x == 0) part[chunk] = v;
 }
@@ -98,7 +113,22 @@ __global__ void __launch_bounds__(kRedThreads) rz_partial_kernel(const Real *__r
 {
   __shared__ Acc sh[kRedThreads];
   Acc rz = Acc(0), rr = Acc(0);
-  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads) {
+  int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x;
+  for (; i + (kUnroll - 1) * kChunkStride < n; i += kUnroll * kChunkStride) {
+    Real rv[kUnroll], dv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      rv[u] = r[i + u * kChunkStride];
+      dv[u] = d[i + u * kChunkStride];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const Acc ri = (Acc)rv[u];
+      rz += ri * (ri / (Acc)dv[u]);
+      rr += ri * ri;
+    }
+  }
+  for (; i < n; i += kChunkStride) {
     const Acc ri = (Acc)r[i];
     rz += ri * (ri / (Acc)d[i]);
     rr += ri * ri;
@@ -121,13 +151,29 @@ __device__ __forceinline__ void cg_update_body(Real *__restrict__ x, Real *__res
   const Acc pq = reduce_partials(pq_part, 1, sh);
   const Acc alpha = scal[cur] / pq;
   Acc rz = Acc(0), rr = Acc(0);
-  for (int64_t i = (int64_t)chunk * kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads) {
-    x[i] = (Real)((Acc)x[i] + alpha * (Acc)p[i]);
-    const Acc ri = (Acc)r[i] - alpha * (Acc)q[i];
-    r[i] = (Real)ri;
-    rz += ri * (ri / (Acc)d[i]);
+  auto one = [&](int64_t j, Real xv, Real pv, Real rv, Real qv, Real dv) {
+    x[j] = (Real)((Acc)xv + alpha * (Acc)pv);
+    const Acc ri = (Acc)rv - alpha * (Acc)qv;
+    r[j] = (Real)ri;
+    rz += ri * (ri / (Acc)dv);
     rr += ri * ri;
+  };
+  int64_t i = (int64_t)chunk * kRedThreads + threadIdx.x;
+  for (; i + (kUnroll - 1) * kChunkStride < n; i += kUnroll * kChunkStride) {
+    Real xv[kUnroll], pv[kUnroll], rv[kUnroll], qv[kUnroll], dv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t j = i + u * kChunkStride;
+      xv[u] = x[j];
+      pv[u] = p[j];
+      rv[u] = r[j];
+      qv[u] = q[j];
+      dv[u] = d[j];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) one(i + u * kChunkStride, xv[u], pv[u], rv[u], qv[u], dv[u]);
   }
+  for (; i < n; i += kChunkStride) one(i, x[i], p[i], r[i], q[i], d[i]);
   rz = block_sum(rz, sh);
   rr = block_sum(rr, sh);
   if (threadIdx.x == 0) {
@@ -158,7 +204,23 @@ __device__ __forceinline__ void cg_pupdate_body(Real *__restrict__ p, const Real
   const Acc rz = reduce_partials(part2, 2, sh);
   const Acc rr = reduce_partials(part2 + 1, 2, sh);
   const Acc beta = use_beta ? rz / scal[cur] : Acc(0);
-  for (int64_t i = (int64_t)chunk * kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads) {
+  int64_t i = (int64_t)chunk * kRedThreads + threadIdx.x;
+  for (; i + (kUnroll - 1) * kChunkStride < n; i += kUnroll * kChunkStride) {
+    Real rv[kUnroll], dv[kUnroll], pv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t j = i + u * kChunkStride;
+      rv[u] = r[j];
+      dv[u] = d[j];
+      pv[u] = p[j];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const Acc z = (Acc)rv[u] / (Acc)dv[u];
+      p[i + u * kChunkStride] = use_beta ? (Real)(z + beta * (Acc)pv[u]) : (Real)z;
+    }
+  }
+  for (; i < n; i += kChunkStride) {
     const Acc z = (Acc)r[i] / (Acc)d[i];
     p[i] = use_beta ? (Real)(z + beta * (Acc)p[i]) : (Real)z;
   }
