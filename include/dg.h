@@ -159,7 +159,7 @@ dg_status dg_error_manufactured(dg_op *op, dg_vec x, void *stream, double err[2]
  *   mode 2: the same split of precisions with reliable updates: one FP32 CG
  *           recurrence whose residual is replaced by the FP64 residual b - A x
  *           (and whose correction is flushed into the FP64 x) each time it has
- *           dropped by the factor rel_tol_inner (e.g. 0.1) since the last
+ *           dropped by the factor rel_tol_inner (e.g. 0.3) since the last
  *           replacement; the search direction is kept across replacements.
  * Stops when ||b - A x||_2 <= rel_tol * ||b||_2 (always checked with an FP64
  * apply).  x holds the initial guess on entry.  Synchronises the stream.

@@ -263,7 +263,7 @@ class Operator:
         if mode is None:
             mode = 1 if mixed else 0
         if rel_tol_inner is None:
-            rel_tol_inner = 0.1 if mode == 2 else 1e-4
+            rel_tol_inner = 0.3 if mode == 2 else 1e-4
         if x is None:
             x = torch.zeros_like(b)
         p = SolveParams(mode, rel_tol, rel_tol_inner, max_iter, max_outer, check_every)
@@ -305,7 +305,7 @@ class Batch:
         self.max_slots = max_slots
         self._keep = {}
 
-    def admit(self, op, b, x, *, rel_tol=1e-8, refine_factor=0.1, max_iter=20000, check_every=10, stream=None):
+    def admit(self, op, b, x, *, rel_tol=1e-8, refine_factor=0.3, max_iter=20000, check_every=10, stream=None):
         p = SolveParams(2, rel_tol, refine_factor, max_iter, 1, check_every)
         slot = ctypes.c_int(-1)
         check(lib().dg_batch_admit(self._h, op.handle, vec(b), vec(x), ctypes.byref(p), ctypes.byref(slot),

@@ -77,7 +77,7 @@ def test_alone_equals_mix_equals_single_solve(dg):
         assert st_mix["iters_inner"] == alone[i][3]["iters_inner"]
     # and the single-request solver in its reliable-update mode
     for i, (op, b, x, st) in enumerate(alone):
-        xs, sts = op.cg_solve(b, mode=2, rel_tol=1e-9, rel_tol_inner=0.1, check_every=10)
+        xs, sts = op.cg_solve(b, mode=2, rel_tol=1e-9, rel_tol_inner=0.3, check_every=10)
         assert sts["converged"]
         assert torch.equal(xs, x), f"request {i}: batch differs from dg_cg_solve"
 
