@@ -1,4 +1,5 @@
-"""FP64 CPU oracle for the SIPG Laplacian (test infrastructure only).
+"""FP64 CPU oracle for the SIPG Laplacian and the upwind advection operator
+(test infrastructure only).
 
 Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It wraps ``liboracle.so`` (built from
@@ -17,6 +18,10 @@ Parity status per function (what pins it is in tests/test_oracle_*.py):
   diag_cells                    pinned: equals the diagonal of the brute-force matrix
   face_point / volume           pinned: boundary area element, mapped volume
   rhs / errors                  pinned: GLL-weight closed form, convergence order
+  apply with op="advection"     pinned: constants map to the inflow flux alone and
+                                the energy identity u^T A u = upwind jump terms
+                                (affine, exact quadrature), convergence order of
+                                the manufactured solve (curved, rotating velocity)
 """
 from __future__ import annotations
 
@@ -32,6 +37,8 @@ _lib = None
 DIRICHLET, NEUMANN = 0, 1
 MAP_AFFINE, MAP_SINE = 0, 1
 COEF_CONST, COEF_SINCOS = 0, 1
+OP_SIPG, OP_ADVECTION = 0, 1
+VEL_CONST, VEL_ROTATION = 0, 1
 
 
 class Problem(ctypes.Structure):
@@ -45,11 +52,17 @@ class Problem(ctypes.Structure):
         ("amplitude", ctypes.c_double),
         ("coef", ctypes.c_int32),
         ("coef_value", ctypes.c_double),
+        ("op", ctypes.c_int32),
+        ("vel", ctypes.c_int32),
+        ("vel_value", ctypes.c_double * 3),
     ]
 
 
 def problem(ncell, degree, *, curved=False, amplitude=0.05, variable_coef=False,
-            coef_value=1.0, bc=(DIRICHLET,) * 6, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
+            coef_value=1.0, bc=(DIRICHLET,) * 6, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+            op="sipg", velocity="rotation"):
+    """op="sipg" (Sec. 2 Eq. (2)) or "advection" (Eq. (1)); for advection the
+    velocity is "rotation" (1/2 - y, x - 1/2, 1/4) or a constant 3-vector."""
     if isinstance(ncell, int):
         ncell = (ncell, ncell, ncell)
     p = Problem()
@@ -62,6 +75,13 @@ def problem(ncell, degree, *, curved=False, amplitude=0.05, variable_coef=False,
     p.amplitude = amplitude
     p.coef = COEF_SINCOS if variable_coef else COEF_CONST
     p.coef_value = coef_value
+    p.op = OP_ADVECTION if op == "advection" else OP_SIPG
+    if isinstance(velocity, str):
+        p.vel = VEL_ROTATION
+        p.vel_value[:] = [0.0, 0.0, 0.0]
+    else:
+        p.vel = VEL_CONST
+        p.vel_value[:] = [float(v) for v in velocity]
     return p
 
 

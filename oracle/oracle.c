@@ -40,6 +40,19 @@
  *     the neighbour's own Jacobian at the same physical point.
  *   - homogeneous Neumann faces contribute nothing.
  *
+ * The same library also evaluates the second operator of the paper, the DG
+ * discretisation of stationary advection with the local Lax-Friedrichs
+ * (upwind) flux, Sec. 2 Eq. (1), in the element form that Algorithm 1 loops
+ * over (problem field op = 1):
+ *     y_i = -(grad phi_i, c u_h)_{Omega_e}
+ *         + <phi_i, 1/2 (c.n)(u- + u+) + 1/2 |c.n| (u- - u+)>_{dOmega_e}
+ *   with n the element's outward normal and u+ the neighbour's trace.
+ *   Readings for it: the velocity c(x) is either a constant vector or the
+ *   divergence-free field c = (1/2 - y, x - 1/2, 1/4) (a rotation about the
+ *   cube's vertical axis with an upward drift); boundary faces take the
+ *   mirror u+ = -u- (bc 0, homogeneous inflow data, as in Algorithm 1's
+ *   boundary loop) or the extrapolation u+ = u- (bc 1, pure outflow).
+ *
  * DoF numbering: global = cell * n^3 + i1 + n*i2 + n^2*i3, cell = cx + Nx*(cy + Ny*cz).
  * Local face numbers 0..5 = x-, x+, y-, y+, z-, z+.
  */
@@ -68,6 +81,9 @@ typedef struct {
   double amplitude;   /* a of the sine map */
   int32_t coef;       /* 0 = constant coef_value, 1 = 1 + 0.5 sin(pi x) cos(pi y) z */
   double coef_value;
+  int32_t op;         /* 0 = SIPG Laplacian, 1 = advection with upwind flux */
+  int32_t vel;        /* advection velocity: 0 = constant vel_value, 1 = (1/2 - y, x - 1/2, 1/4) */
+  double vel_value[3];
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -230,6 +246,8 @@ static int ctx_init(orc_ctx *c, const orc_problem *P)
     if (P->bc[f] != 0 && P->bc[f] != 1) return ORC_ERR_ARG;
   if (P->map != 0 && P->map != 1) return ORC_ERR_ARG;
   if (P->coef != 0 && P->coef != 1) return ORC_ERR_ARG;
+  if (P->op != 0 && P->op != 1) return ORC_ERR_ARG;
+  if (P->vel != 0 && P->vel != 1) return ORC_ERR_ARG;
   int n = P->degree + 1, n2 = n * n, n3 = n2 * n;
   c->n = n;
   c->n3 = n3;
@@ -319,6 +337,18 @@ static double coef_at(const orc_ctx *c, const double x[3])
 {
   if (c->P.coef == 0) return c->P.coef_value;
   return 1.0 + 0.5 * sin(ORC_PI * x[0]) * cos(ORC_PI * x[1]) * x[2];
+}
+
+/* transport velocity of the advection operator at physical point x */
+static void velocity_at(const orc_ctx *c, const double x[3], double v[3])
+{
+  if (c->P.vel == 0) {
+    for (int d = 0; d < 3; ++d) v[d] = c->P.vel_value[d];
+  } else {
+    v[0] = 0.5 - x[1];
+    v[1] = x[0] - 0.5;
+    v[2] = 0.25;
+  }
 }
 
 static void cell_coords(const orc_ctx *c, int64_t e, int ci[3])
@@ -460,6 +490,96 @@ static int local_apply(const orc_ctx *c, int64_t e, const double *u_own,
 }
 
 /* ------------------------------------------------------------------------ */
+/* The element-local advection operator (Sec. 2 Eq. (1), Algorithm 1)        */
+/* ------------------------------------------------------------------------ */
+
+/* Same contract as local_apply, for the advection form.  Cell integral:
+ * -sum_q (J^{-T} grad phi_i) . c u_h det J w.  Faces: at each face point the
+ * upwind flux f* = 1/2 (c.n)(u- + u+) + 1/2 |c.n| (u- - u+) with the
+ * element's outward normal n, tested with phi_i and the area element. */
+static int local_apply_adv(const orc_ctx *c, int64_t e, const double *u_own,
+                           const double *const u_nb[6], double *y, int only_test)
+{
+  const int n = c->n, n2 = n * n, n3 = c->n3;
+  const int ilo = only_test >= 0 ? only_test : 0;
+  const int ihi = only_test >= 0 ? only_test + 1 : n3;
+  int ci[3];
+  cell_coords(c, e, ci);
+  for (int i = ilo; i < ihi; ++i) y[i] = 0.0;
+
+  /* cell term -(grad phi_i, c u_h) */
+  for (int q = 0; q < n3; ++q) {
+    double xi[3] = {c->gx[q % n], c->gx[(q / n) % n], c->gx[q / n2]};
+    double W = c->gw[q % n] * c->gw[(q / n) % n] * c->gw[q / n2];
+    double x[3], J[3][3], Ji[3][3], vel[3];
+    geom_at(c, ci, xi, x, J);
+    double det = inv3(J, Ji);
+    if (!(det > 0.0)) return ORC_ERR_GEOM;
+    double uq = 0.0;
+    for (int j = 0; j < n3; ++j) uq += u_own[j] * c->val[(size_t)q * n3 + j];
+    velocity_at(c, x, vel);
+    for (int i = ilo; i < ihi; ++i) {
+      double gi[3];
+      map_grad(Ji, &c->grad[((size_t)q * n3 + i) * 3], gi);
+      y[i] -= (gi[0] * vel[0] + gi[1] * vel[1] + gi[2] * vel[2]) * uq * det * W;
+    }
+  }
+
+  /* face terms: upwind flux through each of the six faces */
+  for (int f = 0; f < 6; ++f) {
+    const int a = f / 2, side = f % 2;
+    const int64_t nb = neighbour(c, e, f);
+    const int fo = 2 * a + (1 - side);
+    int cn[3] = {ci[0], ci[1], ci[2]};
+    cn[a] += side ? 1 : -1;
+    const double sgn = side ? 1.0 : -1.0;
+    for (int qf = 0; qf < n2; ++qf) {
+      const int q1 = qf % n, q2 = qf / n;
+      double xim[3], x[3], J[3][3], Ji[3][3], vel[3];
+      face_ref_point(c, f, q1, q2, xim);
+      geom_at(c, ci, xim, x, J);
+      double det = inv3(J, Ji);
+      if (!(det > 0.0)) return ORC_ERR_GEOM;
+      double N[3] = {sgn * Ji[a][0], sgn * Ji[a][1], sgn * Ji[a][2]};
+      double nrm = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+      double nv[3] = {N[0] / nrm, N[1] / nrm, N[2] / nrm};
+      double ds = det * nrm * c->gw[q1] * c->gw[q2];
+      const size_t rowm = (size_t)f * n2 + qf;
+      double um = 0.0;
+      for (int j = 0; j < n3; ++j) um += u_own[j] * c->fval[rowm * n3 + j];
+      double up;
+      if (nb >= 0) {
+        double xip[3], xp[3], Jp[3][3];
+        face_ref_point(c, fo, q1, q2, xip);
+        geom_at(c, cn, xip, xp, Jp);
+        double dx = fabs(xp[0] - x[0]) + fabs(xp[1] - x[1]) + fabs(xp[2] - x[2]);
+        if (dx > 1e-12 * (1.0 + fabs(x[0]) + fabs(x[1]) + fabs(x[2]))) return ORC_ERR_GEOM;
+        const size_t rowp = (size_t)fo * n2 + qf;
+        const double *un = u_nb[f];
+        up = 0.0;
+        if (un)
+          for (int j = 0; j < n3; ++j) up += un[j] * c->fval[rowp * n3 + j];
+      } else {
+        up = (c->P.bc[f] == 0) ? -um : um;   /* mirror (inflow data 0) or outflow */
+      }
+      velocity_at(c, x, vel);
+      const double vn = vel[0] * nv[0] + vel[1] * nv[1] + vel[2] * nv[2];
+      const double flux = 0.5 * vn * (um + up) + 0.5 * fabs(vn) * (um - up);
+      for (int i = ilo; i < ihi; ++i) y[i] += c->fval[rowm * n3 + i] * flux * ds;
+    }
+  }
+  return ORC_OK;
+}
+
+/* the operator selected by the problem */
+static int local_op(const orc_ctx *c, int64_t e, const double *u_own, const double *const u_nb[6], double *y,
+                    int only_test)
+{
+  return c->P.op == 1 ? local_apply_adv(c, e, u_own, u_nb, y, only_test)
+                      : local_apply(c, e, u_own, u_nb, y, only_test);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Exported entry points                                                     */
 /* ------------------------------------------------------------------------ */
 
@@ -496,7 +616,7 @@ int orc_apply_cells(const orc_problem *P, const double *src, const int64_t *cell
       int64_t nb = neighbour(&c, e, f);
       unb[f] = nb >= 0 ? src + nb * c.n3 : NULL;
     }
-    int r = local_apply(&c, e, src + e * c.n3, unb, dst_rows + l * c.n3, -1);
+    int r = local_op(&c, e, src + e * c.n3, unb, dst_rows + l * c.n3, -1);
     if (r) err = r;
   }
   ctx_free(&c);
@@ -534,7 +654,7 @@ int orc_diag_cells(const orc_problem *P, const int64_t *cells, int64_t ncells, d
       if (e < 0 || e >= total) { err = ORC_ERR_ARG; continue; }
       for (int i = 0; i < c.n3; ++i) {
         u[i] = 1.0;
-        int r = local_apply(&c, e, u, none, y, i);
+        int r = local_op(&c, e, u, none, y, i);
         if (r) err = r;
         diag_rows[l * c.n3 + i] = y[i];
         u[i] = 0.0;
@@ -578,7 +698,7 @@ int orc_block_rows(const orc_problem *P, const int64_t *cells, int64_t ncells, d
           const double *uown = zero;
           unit[j] = 1.0;
           if (blk == 0) uown = unit; else unb[blk - 1] = unit;
-          int r = local_apply(&c, e, uown, unb, y, -1);
+          int r = local_op(&c, e, uown, unb, y, -1);
           if (r) err = r;
           for (int i = 0; i < n3; ++i) B[(size_t)blk * bs + (size_t)i * n3 + j] = y[i];
           unit[j] = 0.0;
@@ -690,12 +810,26 @@ static double forcing(const orc_ctx *c, const double x[3])
   return -(gc[0] * g[0] + gc[1] * g[1] + gc[2] * g[2]) + 3.0 * ORC_PI * ORC_PI * cv * u;
 }
 
+/* advection: f = div(c u*) = c . grad u* for the divergence-free velocities */
+static double forcing_adv(const orc_ctx *c, const double x[3])
+{
+  double u, g[3], v[3];
+  exact_u(x, &u, g);
+  velocity_at(c, x, v);
+  return v[0] * g[0] + v[1] * g[1] + v[2] * g[2];
+}
+
+static double forcing_op(const orc_ctx *c, const double x[3])
+{
+  return c->P.op == 1 ? forcing_adv(c, x) : forcing(c, x);
+}
+
 double orc_forcing_at(const orc_problem *P, const double *x)
 {
   orc_ctx c;
   memset(&c, 0, sizeof(c));
   c.P = *P;
-  return forcing(&c, x);
+  return forcing_op(&c, x);
 }
 
 /* b_i = sum_q f(x_q) phi_i(xi_q) det J w_q  (homogeneous Dirichlet data). */
@@ -716,7 +850,7 @@ int orc_rhs(const orc_problem *P, double *b)
       double xi[3] = {c.gx[q % n], c.gx[(q / n) % n], c.gx[q / n2]};
       double x[3], J[3][3], Ji[3][3];
       geom_at(&c, ci, xi, x, J);
-      double fac = forcing(&c, x) * inv3(J, Ji) * c.gw[q % n] * c.gw[(q / n) % n] * c.gw[q / n2];
+      double fac = forcing_op(&c, x) * inv3(J, Ji) * c.gw[q % n] * c.gw[(q / n) % n] * c.gw[q / n2];
       for (int i = 0; i < n3; ++i) be[i] += fac * c.val[(size_t)q * n3 + i];
     }
   }
