@@ -127,12 +127,42 @@ dg_status dg_setup(const dg_mesh *mesh, int degree, const dg_geometry *geom,
                    const dg_coefficient *coef, unsigned precisions, const dg_allocator *alloc,
                    void *stream, dg_op **out);
 
+/* Transport velocity of the advection operator (Sec. 2, Eq. (1)).
+ * DG_VEL_CONST: c = value (a constant vector).
+ * DG_VEL_ROTATION: c(x) = (1/2 - y, x - 1/2, 1/4), a divergence-free
+ * rotation about the unit cube's vertical axis with an upward drift
+ * (value ignored). */
+typedef enum { DG_VEL_CONST = 0, DG_VEL_ROTATION = 1 } dg_velocity_kind;
+typedef struct {
+  dg_velocity_kind kind;
+  double value[3];
+} dg_velocity;
+
+/* Bytes of device memory dg_setup_advection will allocate: 3 values per cell
+ * quadrature point (J^{-1} c det J w) and 1 per face point ((c . n) ds for
+ * the +e_a orientation of the face), in each enabled precision. */
+dg_status dg_footprint_advection(const dg_mesh *mesh, int degree, const dg_geometry *geom,
+                                 const dg_velocity *vel, unsigned precisions, size_t *bytes);
+
+/* Builds the DG advection operator with the local Lax-Friedrichs (upwind)
+ * flux of Sec. 2, Eq. (1), whose loop structure is Algorithm 1:
+ *   y_i = -(grad phi_i, c u_h)_e + <phi_i, 1/2 (c.n)(u- + u+) + 1/2 |c.n| (u- - u+)>_{de}.
+ * Boundary faces take u+ = -u- (mirror, homogeneous inflow data) where
+ * mesh->bc is DG_BC_DIRICHLET and u+ = u- (outflow) where it is
+ * DG_BC_NEUMANN.  geom->storage is ignored.  The op works with dg_apply,
+ * dg_n_dofs and dg_destroy; dg_diagonal, dg_rhs, dg_error_manufactured,
+ * dg_cg_solve and dg_batch_admit return DG_ERR_UNSUPPORTED for it (the
+ * operator is not symmetric). */
+dg_status dg_setup_advection(const dg_mesh *mesh, int degree, const dg_geometry *geom, const dg_velocity *vel,
+                             unsigned precisions, const dg_allocator *alloc, void *stream, dg_op **out);
+
 /* Number of degrees of freedom (ncells * (k+1)^3); -1 for a NULL op. */
 int64_t dg_n_dofs(const dg_op *op);
 
-/* dst := A src (Sec. 2, Eq. (3)), one fused pass over all cells: each cell
- * computes its cell integral and the own-side share of its six face integrals
- * (Algorithm 1, steps (ii)-(iv)) and writes its dst block once; dst need not be
+/* dst := A src (Sec. 2, Eq. (3)) for the op's operator (SIPG Laplacian or
+ * advection), one fused pass over all cells: each cell computes its cell
+ * integral and the own-side share of its six face integrals (Algorithm 1,
+ * steps (ii)-(iv)) and writes its dst block once; dst need not be
  * initialised.  src and dst must have the same dtype, which must be enabled in
  * the op, length dg_n_dofs, and must not alias: otherwise DG_ERR_ARG and nothing
  * is enqueued. */

@@ -42,6 +42,26 @@ class Coefficient(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("value", ctypes.c_double)]
 
 
+VEL_CONST, VEL_ROTATION = 0, 1
+
+
+class Velocity(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("value", ctypes.c_double * 3)]
+
+
+def _velocity(velocity):
+    """"rotation" (c = (1/2 - y, x - 1/2, 1/4)) or a constant 3-vector."""
+    v = Velocity()
+    if isinstance(velocity, str):
+        if velocity != "rotation":
+            raise ValueError("velocity must be 'rotation' or a 3-vector")
+        v.kind = VEL_ROTATION
+    else:
+        v.kind = VEL_CONST
+        v.value[:] = [float(c) for c in velocity]
+    return v
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -76,6 +96,12 @@ _SIGS = [
     ("dg_setup", ctypes.c_int, [ctypes.POINTER(Mesh), ctypes.c_int, ctypes.POINTER(Geometry),
                                 ctypes.POINTER(Coefficient), ctypes.c_uint, ctypes.POINTER(Allocator), _P,
                                 ctypes.POINTER(_P)]),
+    ("dg_footprint_advection", ctypes.c_int, [ctypes.POINTER(Mesh), ctypes.c_int, ctypes.POINTER(Geometry),
+                                              ctypes.POINTER(Velocity), ctypes.c_uint,
+                                              ctypes.POINTER(ctypes.c_size_t)]),
+    ("dg_setup_advection", ctypes.c_int, [ctypes.POINTER(Mesh), ctypes.c_int, ctypes.POINTER(Geometry),
+                                          ctypes.POINTER(Velocity), ctypes.c_uint, ctypes.POINTER(Allocator), _P,
+                                          ctypes.POINTER(_P)]),
     ("dg_n_dofs", ctypes.c_int64, [_P]),
     ("dg_apply", ctypes.c_int, [_P, Vec, Vec, _P]),
     ("dg_diagonal", ctypes.c_int, [_P, Vec, _P]),
@@ -150,6 +176,17 @@ def footprint(ncell, degree, *, curved=False, amplitude=0.05, variable_coef=Fals
     out = ctypes.c_size_t()
     check(lib().dg_footprint(ctypes.byref(m), degree, ctypes.byref(g), ctypes.byref(c), precisions,
                              ctypes.byref(out)))
+    return out.value
+
+
+def footprint_advection(ncell, degree, *, curved=False, amplitude=0.05, velocity="rotation",
+                        precisions=PREC_F64 | PREC_F32, bc=(DIRICHLET,) * 6):
+    m = make_mesh(ncell, bc)
+    g = Geometry(MAP_SINE if curved else MAP_AFFINE, amplitude, STORE_JACOBIAN)
+    v = _velocity(velocity)
+    out = ctypes.c_size_t()
+    check(lib().dg_footprint_advection(ctypes.byref(m), degree, ctypes.byref(g), ctypes.byref(v), precisions,
+                                       ctypes.byref(out)))
     return out.value
 
 
@@ -275,6 +312,57 @@ class Operator:
         out["converged"] = rc == DG_OK
         out["mode"] = mode
         return x, out
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().dg_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class AdvectionOperator:
+    """The DG advection operator with the upwind flux (Sec. 2, Eq. (1))
+    resident on the GPU.  bc 0 faces take the mirror u+ = -u- (homogeneous
+    inflow data), bc 1 faces u+ = u- (outflow)."""
+
+    def __init__(self, ncell, degree, *, curved=False, amplitude=0.05, velocity="rotation",
+                 bc=(DIRICHLET,) * 6, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                 precisions=PREC_F64 | PREC_F32, torch_alloc=True, stream=None):
+        self._h = None
+        self.degree = degree
+        self.mesh = make_mesh(ncell, bc, lo, hi)
+        self.ncell = tuple(self.mesh.ncell)
+        self.curved = curved
+        self.velocity = velocity
+        self.precisions = precisions
+        self._alloc = TorchAllocator() if torch_alloc else None
+        g = Geometry(MAP_SINE if curved else MAP_AFFINE, amplitude, STORE_JACOBIAN)
+        v = _velocity(velocity)
+        h = ctypes.c_void_p()
+        check(lib().dg_setup_advection(ctypes.byref(self.mesh), degree, ctypes.byref(g), ctypes.byref(v), precisions,
+                                       ctypes.byref(self._alloc.struct) if self._alloc else None, _stream(stream),
+                                       ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n_dofs(self):
+        return int(lib().dg_n_dofs(self._h))
+
+    def apply(self, src, dst=None, stream=None):
+        torch = _torch()
+        if dst is None:
+            dst = torch.empty_like(src)
+        check(lib().dg_apply(self._h, vec(src), vec(dst), _stream(stream)))
+        return dst
 
     def close(self):
         if self._h is not None and self._h.value:

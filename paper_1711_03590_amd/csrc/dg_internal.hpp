@@ -18,13 +18,18 @@ namespace dgk {
 //                 face: j = J^{-1} n (3, Design Choice 5) and c * ds per face point
 //   CURVED_MERGED G4: the symmetric c * det J * w * J^{-1} J^{-T} (6) per cell
 //                 point; faces as CURVED
-enum GeomKind : int { AFFINE_CONST = 0, AFFINE_VAR = 1, CURVED = 2, CURVED_MERGED = 3 };
+//   ADVECTION     the advection operator (Sec. 2, Eq. (1)): J^{-1} c det J w
+//                 (3) per cell point, (c . n) ds for the +e_a normal per face point
+enum GeomKind : int { AFFINE_CONST = 0, AFFINE_VAR = 1, CURVED = 2, CURVED_MERGED = 3, ADVECTION = 4 };
 
 // faces carry j = J^{-1} n and c ds per point
 constexpr bool curved_faces(int gk) { return gk == CURVED || gk == CURVED_MERGED; }
 // stored values per cell quadrature point
-constexpr int cell_values(int gk) { return gk == CURVED ? 10 : (gk == CURVED_MERGED ? 6 : (gk == AFFINE_VAR ? 1 : 0)); }
-constexpr int face_values(int gk) { return curved_faces(gk) ? 4 : (gk == AFFINE_VAR ? 1 : 0); }
+constexpr int cell_values(int gk)
+{
+  return gk == CURVED ? 10 : (gk == CURVED_MERGED ? 6 : (gk == ADVECTION ? 3 : (gk == AFFINE_VAR ? 1 : 0)));
+}
+constexpr int face_values(int gk) { return curved_faces(gk) ? 4 : ((gk == AFFINE_VAR || gk == ADVECTION) ? 1 : 0); }
 
 constexpr int kMinN = 2;  // degree 1
 constexpr int kMaxN = 9;  // degree 8
@@ -64,6 +69,7 @@ struct dg_op {
   int degree = 0, n = 0;
   dg_geometry geom;
   dg_coefficient coef;
+  dg_velocity vel{};         // advection ops only
   unsigned precisions = 0;
   int gk = 0;
   int64_t ncells = 0, ndofs = 0, nfaces[3] = {0, 0, 0};

@@ -134,6 +134,8 @@ struct GeoArgs {
   double lo[3], h[3];
   int map, coef;
   double amp, cval;
+  int vel;            // advection velocity kind
+  double vval[3];
   Rule1D rule;
 };
 
@@ -159,6 +161,18 @@ __device__ __forceinline__ void map_point(const GeoArgs &g, const double X[3], d
   for (int i = 0; i < 3; ++i) {
     x[i] = X[i] + disp;
     for (int j = 0; j < 3; ++j) Ginv[i][j] = ((i == j) ? 1.0 : 0.0) - ds[j] * inv;
+  }
+}
+
+// transport velocity of the advection operator at the physical point x
+__device__ __forceinline__ void velocity_value(const GeoArgs &g, const double x[3], double v[3])
+{
+  if (g.vel == DG_VEL_CONST) {
+    for (int d = 0; d < 3; ++d) v[d] = g.vval[d];
+  } else {
+    v[0] = 0.5 - x[1];
+    v[1] = x[0] - 0.5;
+    v[2] = 0.25;
   }
 }
 
@@ -194,6 +208,16 @@ __global__ void geom_cells_kernel(const GeoArgs g, int64_t npts, double *o64, fl
       }
     if (o64) o64[9 * stride + idx] = cjxw;
     if (o32) o32[9 * stride + idx] = (float)cjxw;
+  } else if (GK == ADVECTION) {
+    // t = J^{-1} c det J w: J^{-1}[b][c] = Ginv[b][c] / h_b
+    double v[3];
+    velocity_value(g, x, v);
+    const double jxw = detG * g.h[0] * g.h[1] * g.h[2] * W;
+    for (int b = 0; b < 3; ++b) {
+      const double t = (Gi[b][0] * v[0] + Gi[b][1] * v[1] + Gi[b][2] * v[2]) / g.h[b] * jxw;
+      if (o64) o64[b * stride + idx] = t;
+      if (o32) o32[b * stride + idx] = (float)t;
+    }
   } else if (GK == CURVED_MERGED) {
     // M = c det J w J^{-1} J^{-T}: M[b][c] = cjxw sum_a J^{-T}[a][b] J^{-T}[a][c]
     double jt[3][3];
@@ -249,6 +273,15 @@ __global__ void geom_faces_kernel(const GeoArgs g, int a, int64_t npts, double *
     }
     if (o64) o64[3 * stride + idx] = cds;
     if (o32) o32[3 * stride + idx] = (float)cds;
+  } else if (GK == ADVECTION) {
+    // (c . n) ds for the +e_a normal: Nanson, n ds = det J J^{-T} e_a w, and
+    // (J^{-T} e_a)_b = J^{-1}[a][b] = Ginv[a][b] / h_a
+    double v[3];
+    velocity_value(g, x, v);
+    const double cn = detG * g.h[0] * g.h[1] * g.h[2] * w *
+                      (Gi[a][0] * v[0] + Gi[a][1] * v[1] + Gi[a][2] * v[2]) / g.h[a];
+    if (o64) o64[idx] = cn;
+    if (o32) o32[idx] = (float)cn;
   } else {
     const double cds = c * g.h[t1] * g.h[t2] * w;
     if (o64) o64[idx] = cds;
@@ -398,6 +431,8 @@ static GeoArgs geo_args(const dg_op *op)
   g.amp = op->geom.amplitude;
   g.coef = op->coef.kind;
   g.cval = op->coef.value;
+  g.vel = op->vel.kind;
+  for (int d = 0; d < 3; ++d) g.vval[d] = op->vel.value[d];
   rule_for(op->n, g.rule);
   return g;
 }
@@ -498,6 +533,21 @@ dg_status dg_footprint(const dg_mesh *mesh, int degree, const dg_geometry *geom,
   return DG_OK;
 }
 
+dg_status dg_footprint_advection(const dg_mesh *mesh, int degree, const dg_geometry *geom, const dg_velocity *vel,
+                                 unsigned precisions, size_t *bytes)
+{
+  const dg_coefficient one{DG_COEF_CONST, 1.0};
+  dg_status st = validate(mesh, degree, geom, &one, precisions);
+  if (st != DG_OK) return st;
+  if (!vel || (vel->kind != DG_VEL_CONST && vel->kind != DG_VEL_ROTATION)) return fail(DG_ERR_ARG, "bad velocity");
+  if (!bytes) return fail(DG_ERR_ARG, "bytes is null");
+  const int64_t nc[3] = {mesh->ncell[0], mesh->ncell[1], mesh->ncell[2]};
+  *bytes = footprint_bytes(nc, degree + 1, ADVECTION, precisions) -
+           (size_t)(nc[0] * nc[1] * nc[2]) * (degree + 1) * (degree + 1) * (degree + 1) *
+               (((precisions & DG_PREC_F64) ? 8 : 0) + ((precisions & DG_PREC_F32) ? 4 : 0));  // no diagonal
+  return DG_OK;
+}
+
 int64_t dg_n_dofs(const dg_op *op) { return op ? op->ndofs : -1; }
 
 dg_status dg_destroy(dg_op *op)
@@ -513,8 +563,12 @@ dg_status dg_destroy(dg_op *op)
   return DG_OK;
 }
 
-dg_status dg_setup(const dg_mesh *mesh, int degree, const dg_geometry *geom, const dg_coefficient *coef,
-                   unsigned precisions, const dg_allocator *alloc, void *stream, dg_op **out)
+}  // extern "C"
+
+// the SIPG op (vel == nullptr) or the advection op with velocity vel
+static dg_status setup_impl(const dg_mesh *mesh, int degree, const dg_geometry *geom, const dg_coefficient *coef,
+                            const dg_velocity *vel, unsigned precisions, const dg_allocator *alloc, void *stream,
+                            dg_op **out)
 {
   dg_status st = validate(mesh, degree, geom, coef, precisions);
   if (st != DG_OK) return st;
@@ -527,8 +581,9 @@ dg_status dg_setup(const dg_mesh *mesh, int degree, const dg_geometry *geom, con
   op->n = degree + 1;
   op->geom = *geom;
   op->coef = *coef;
+  if (vel) op->vel = *vel;
   op->precisions = precisions;
-  op->gk = geom_kind(geom, coef);
+  op->gk = vel ? ADVECTION : geom_kind(geom, coef);
   if (alloc) {
     op->alloc = *alloc;
     op->own_alloc = false;
@@ -586,6 +641,8 @@ dg_status dg_setup(const dg_mesh *mesh, int degree, const dg_geometry *geom, con
     if (op->gk == CURVED) hipLaunchKernelGGL(geom_cells_kernel<CURVED>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
     else if (op->gk == CURVED_MERGED)
       hipLaunchKernelGGL(geom_cells_kernel<CURVED_MERGED>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
+    else if (op->gk == ADVECTION)
+      hipLaunchKernelGGL(geom_cells_kernel<ADVECTION>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
     else hipLaunchKernelGGL(geom_cells_kernel<AFFINE_VAR>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cleanup(hip_fail(e, "geometry kernel"));
@@ -597,6 +654,8 @@ dg_status dg_setup(const dg_mesh *mesh, int degree, const dg_geometry *geom, con
       double *o64 = static_cast<double *>(op->face_geo[0][a]);
       float *o32 = static_cast<float *>(op->face_geo[1][a]);
       if (curved_faces(op->gk)) hipLaunchKernelGGL(geom_faces_kernel<CURVED>, dim3(grid), dim3(256), 0, s, g, a, npts, o64, o32, npts);
+      else if (op->gk == ADVECTION)
+        hipLaunchKernelGGL(geom_faces_kernel<ADVECTION>, dim3(grid), dim3(256), 0, s, g, a, npts, o64, o32, npts);
       else hipLaunchKernelGGL(geom_faces_kernel<AFFINE_VAR>, dim3(grid), dim3(256), 0, s, g, a, npts, o64, o32, npts);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return cleanup(hip_fail(e, "face geometry kernel"));
@@ -611,13 +670,13 @@ dg_status dg_setup(const dg_mesh *mesh, int degree, const dg_geometry *geom, con
     op->v64.g.face_stride[a] = op->nfaces[a] * n2;
     op->v32.g.face_stride[a] = op->nfaces[a] * n2;
   }
-  // Jacobi diagonal in the enabled precisions
-  for (int p = 0; p < 2; ++p) {
-    if (!(precisions & (1u << p))) continue;
-    op->diag[p] = op_alloc(op, op->ndofs * (p == 0 ? 8 : 4));
-    if (!op->diag[p]) return cleanup(fail(DG_ERR_OOM, "diagonal allocation failed"));
-  }
-  {
+  // Jacobi diagonal in the enabled precisions (the SIPG operator only)
+  if (!vel) {
+    for (int p = 0; p < 2; ++p) {
+      if (!(precisions & (1u << p))) continue;
+      op->diag[p] = op_alloc(op, op->ndofs * (p == 0 ? 8 : 4));
+      if (!op->diag[p]) return cleanup(fail(DG_ERR_OOM, "diagonal allocation failed"));
+    }
     hipError_t e = launch_diag_any(op, op->diag[0], op->diag[1], s);
     if (e != hipSuccess) return cleanup(hip_fail(e, "diagonal kernel"));
   }
@@ -637,6 +696,22 @@ dg_status dg_setup(const dg_mesh *mesh, int degree, const dg_geometry *geom, con
   if (!op->scratch) return cleanup(fail(DG_ERR_OOM, "scratch allocation failed"));
   *out = op;
   return DG_OK;
+}
+
+extern "C" {
+
+dg_status dg_setup(const dg_mesh *mesh, int degree, const dg_geometry *geom, const dg_coefficient *coef,
+                   unsigned precisions, const dg_allocator *alloc, void *stream, dg_op **out)
+{
+  return setup_impl(mesh, degree, geom, coef, nullptr, precisions, alloc, stream, out);
+}
+
+dg_status dg_setup_advection(const dg_mesh *mesh, int degree, const dg_geometry *geom, const dg_velocity *vel,
+                             unsigned precisions, const dg_allocator *alloc, void *stream, dg_op **out)
+{
+  if (!vel || (vel->kind != DG_VEL_CONST && vel->kind != DG_VEL_ROTATION)) return fail(DG_ERR_ARG, "bad velocity");
+  const dg_coefficient one{DG_COEF_CONST, 1.0};
+  return setup_impl(mesh, degree, geom, &one, vel, precisions, alloc, stream, out);
 }
 
 static dg_status check_vec(const dg_op *op, const dg_vec &v, const char *name)
@@ -668,6 +743,7 @@ dg_status dg_apply(dg_op *op, dg_vec src, dg_vec dst, void *stream)
 dg_status dg_diagonal(dg_op *op, dg_vec diag, void *stream)
 {
   if (!op) return fail(DG_ERR_ARG, "op is null");
+  if (op->gk == ADVECTION) return fail(DG_ERR_UNSUPPORTED, "the advection operator has no Jacobi diagonal here");
   dg_status st = check_vec(op, diag, "diag");
   if (st != DG_OK) return st;
   const int p = diag.dtype == DG_F32 ? 1 : 0;
@@ -680,6 +756,7 @@ dg_status dg_diagonal(dg_op *op, dg_vec diag, void *stream)
 dg_status dg_rhs(dg_op *op, dg_vec b, void *stream)
 {
   if (!op) return fail(DG_ERR_ARG, "op is null");
+  if (op->gk == ADVECTION) return fail(DG_ERR_UNSUPPORTED, "dg_rhs is defined for the SIPG operator");
   dg_status st = check_vec(op, b, "b");
   if (st != DG_OK) return st;
   if (b.dtype != DG_F64) return fail(DG_ERR_ARG, "b must be FP64");
@@ -706,6 +783,7 @@ dg_status dg_rhs(dg_op *op, dg_vec b, void *stream)
 dg_status dg_error_manufactured(dg_op *op, dg_vec x, void *stream, double err[2])
 {
   if (!op) return fail(DG_ERR_ARG, "op is null");
+  if (op->gk == ADVECTION) return fail(DG_ERR_UNSUPPORTED, "dg_error_manufactured is defined for the SIPG operator");
   dg_status st = check_vec(op, x, "x");
   if (st != DG_OK) return st;
   if (x.dtype != DG_F64) return fail(DG_ERR_ARG, "x must be FP64");

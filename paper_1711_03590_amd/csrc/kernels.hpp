@@ -815,6 +815,12 @@ sipg_diag_kernel(const OpView<double> op, double *__restrict__ d64, float *__res
   if (d32) d32[o] = (float)acc;
 }
 
+}  // namespace dgk
+
+#include "advection.hpp"
+
+namespace dgk {
+
 template <int N>
 hipError_t launch_apply(const dg_op *op, const void *src, void *dst, bool f32, hipStream_t s)
 {
@@ -827,6 +833,7 @@ hipError_t launch_apply(const dg_op *op, const void *src, void *dst, bool f32, h
     switch (op->gk) {
       case CURVED: hipLaunchKernelGGL((sipg_apply_kernel<N, float, CURVED>), dim3(grid), dim3(BK::TPB), 0, s, op->v32, x, y); break;
       case CURVED_MERGED: hipLaunchKernelGGL((sipg_apply_kernel<N, float, CURVED_MERGED>), dim3(grid), dim3(BK::TPB), 0, s, op->v32, x, y); break;
+      case ADVECTION: hipLaunchKernelGGL((adv_apply_kernel<N, float>), dim3(grid), dim3(BK::TPB), 0, s, op->v32, x, y); break;
       case AFFINE_VAR: hipLaunchKernelGGL((sipg_apply_kernel<N, float, AFFINE_VAR>), dim3(grid), dim3(BK::TPB), 0, s, op->v32, x, y); break;
       default: hipLaunchKernelGGL((sipg_apply_kernel<N, float, AFFINE_CONST>), dim3(grid), dim3(BK::TPB), 0, s, op->v32, x, y); break;
     }
@@ -836,6 +843,7 @@ hipError_t launch_apply(const dg_op *op, const void *src, void *dst, bool f32, h
     switch (op->gk) {
       case CURVED: hipLaunchKernelGGL((sipg_apply_kernel<N, double, CURVED>), dim3(grid), dim3(BK::TPB), 0, s, op->v64, x, y); break;
       case CURVED_MERGED: hipLaunchKernelGGL((sipg_apply_kernel<N, double, CURVED_MERGED>), dim3(grid), dim3(BK::TPB), 0, s, op->v64, x, y); break;
+      case ADVECTION: hipLaunchKernelGGL((adv_apply_kernel<N, double>), dim3(grid), dim3(BK::TPB), 0, s, op->v64, x, y); break;
       case AFFINE_VAR: hipLaunchKernelGGL((sipg_apply_kernel<N, double, AFFINE_VAR>), dim3(grid), dim3(BK::TPB), 0, s, op->v64, x, y); break;
       default: hipLaunchKernelGGL((sipg_apply_kernel<N, double, AFFINE_CONST>), dim3(grid), dim3(BK::TPB), 0, s, op->v64, x, y); break;
     }

@@ -107,3 +107,28 @@ def test_bad_storage_rejected(dg):
     out = ctypes.c_size_t()
     st = dg.lib().dg_footprint(ctypes.byref(m), 3, ctypes.byref(g), ctypes.byref(c), dg.PREC_F64, ctypes.byref(out))
     assert st == dg.DG_ERR_ARG
+
+
+def test_footprint_advection(dg):
+    # 3 values per cell point (J^{-1} c det J w), 1 per face point, no diagonal
+    k, N = 4, 32
+    n = k + 1
+    cells = N ** 3
+    faces = 3 * N * N * (N + 1)
+    vals = 3 * cells * n ** 3 + faces * n ** 2
+    assert dg.footprint_advection(N, k, curved=True) == vals * 12
+    assert dg.footprint_advection(N, k, velocity=(1.0, 0.0, 0.0), precisions=dg.PREC_F32) == vals * 4
+    with pytest.raises(ValueError):
+        dg.footprint_advection(N, k, velocity="spin")
+
+
+def test_bad_velocity_rejected(dg):
+    import ctypes
+    m = dg.make_mesh(4, (dg.DIRICHLET,) * 6)
+    g = dg.Geometry(dg.MAP_SINE, 0.05, 0)
+    v = dg.Velocity()
+    v.kind = 5
+    out = ctypes.c_size_t()
+    st = dg.lib().dg_footprint_advection(ctypes.byref(m), 3, ctypes.byref(g), ctypes.byref(v), dg.PREC_F64,
+                                         ctypes.byref(out))
+    assert st == dg.DG_ERR_ARG
