@@ -33,7 +33,8 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1711_03590_amd", "csrc", "kernels.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sipg_apply_f64_curved_k4_32cubed_traffic.txt")
 
 
-GEOMETRY_VALUES = {"curved": (10, 4), "curved-merged": (6, 4), "affine-variable": (1, 1), "affine": (0, 0)}
+GEOMETRY_VALUES = {"curved": (10, 4), "curved-merged": (6, 4), "affine-variable": (1, 1), "affine": (0, 0),
+                   "advection": (3, 1)}
 
 
 def algorithmic_bytes_per_dof(ncell, k, real_bytes, geometry="curved"):
@@ -42,8 +43,9 @@ def algorithmic_bytes_per_dof(ncell, k, real_bytes, geometry="curved"):
     quadrature point (n.J^{-1}, c ds); affine with a variable coefficient:
     c det J w per cell point and c ds per face point; affine with a constant
     coefficient: nothing.  Merged curved storage (G4): the 6 entries of the
-    symmetric c det J w J^{-1} J^{-T} per cell point, faces as G3.  Neighbour
-    re-reads and tables are not counted."""
+    symmetric c det J w J^{-1} J^{-T} per cell point, faces as G3.  The
+    advection operator: J^{-1} c det J w per cell point and (c.n) ds per face
+    point.  Neighbour re-reads and tables are not counted."""
     n = k + 1
     cells = ncell ** 3
     faces = 3 * ncell * ncell * (ncell + 1)
@@ -205,9 +207,10 @@ def main():
 
     del flush
     hbm = measure_hbm(torch)
-    variants = merged = None
+    variants = merged = advection = None
     if args.variants:
         merged = bench_merged(dg, torch, synth, N, k, args.steps, args.warmup, res)
+        advection = bench_advection(dg, torch, synth, N, k, args.steps, args.warmup)
         variants = bench_variants(dg, torch, synth, k)
 
     if args.copy_calibration:
@@ -262,6 +265,8 @@ def main():
                         "per_launch_us": r["per_launch_us"], "speedup_vs_fp64": r["dofs"] / head["dofs"]}
     if merged:
         line["merged_geometry"] = merged
+    if advection:
+        line["advection"] = advection
     if variants:
         line["geometry_variants"] = variants
     if solve:
@@ -322,6 +327,27 @@ def bench_merged(dg, torch, synth, ncell, k, steps, warmup, g3):
                      "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
         if prec in g3:
             out[prec]["speedup_vs_g3"] = out[prec]["dofs_per_s"] / g3[prec]["dofs"]
+        del x, y
+    op.close()
+    return out
+
+
+def bench_advection(dg, torch, synth, ncell, k, steps, warmup):
+    """The advection operator with the upwind flux (Sec. 2 Eq. (1)) on the
+    headline mesh: rotating velocity, FP64 and FP32."""
+    op = dg.AdvectionOperator(ncell, k, curved=True, amplitude=synth.AMPLITUDE, velocity="rotation")
+    nd = op.n_dofs
+    src = synth.src_vector(nd, synth.seed_for(6, k))
+    out = {"workload": f"{ncell}^3 sine-curved, k={k}, upwind advection, c = (1/2 - y, x - 1/2, 1/4)"}
+    for prec in ("f64", "f32"):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        x = torch.from_numpy(src).to(dtype=dt, device="cuda")
+        y = torch.empty_like(x)
+        ms = time_apply(op, x, y, steps, warmup, torch)
+        bpd = algorithmic_bytes_per_dof(ncell, k, 8 if prec == "f64" else 4, "advection")
+        gbs = bpd * nd / (ms * 1e-3) / 1e9
+        out[prec] = {"dofs_per_s": nd / (ms * 1e-3), "us": ms * 1e3, "algorithmic_bytes_per_dof": bpd,
+                     "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
         del x, y
     op.close()
     return out
