@@ -49,6 +49,10 @@ template <typename Real, typename Acc>
 __device__ __forceinline__ void dot_partial_body(const Real *__restrict__ x, const Real *__restrict__ y, int64_t n,
                                                  Acc *__restrict__ part, int chunk, Acc *sh)
 {
+  if ((int64_t)chunk * kRedThreads >= n) {  // an empty chunk (short vectors): its partial is zero
+    if (threadIdx.x == 0) part[chunk] = Acc(0);
+    return;
+  }
   Acc v = Acc(0);
   int64_t i = (int64_t)chunk * kRedThreads + threadIdx.x;
   for (; i + (kUnroll - 1) * kChunkStride < n; i += kUnroll * kChunkStride) {
@@ -148,6 +152,10 @@ __device__ __forceinline__ void cg_update_body(Real *__restrict__ x, Real *__res
                                                const Acc *__restrict__ pq_part, const Acc *scal, int cur,
                                                Acc *__restrict__ part2, int chunk, Acc *sh)
 {
+  if ((int64_t)chunk * kRedThreads >= n) {  // an empty chunk needs no alpha
+    if (threadIdx.x == 0) part2[2 * chunk] = part2[2 * chunk + 1] = Acc(0);
+    return;
+  }
   const Acc pq = reduce_partials(pq_part, 1, sh);
   const Acc alpha = scal[cur] / pq;
   Acc rz = Acc(0), rr = Acc(0);
@@ -201,6 +209,7 @@ __device__ __forceinline__ void cg_pupdate_body(Real *__restrict__ p, const Real
                                                 const Real *__restrict__ d, int64_t n, const Acc *__restrict__ part2,
                                                 Acc *scal, int use_beta, int cur, int chunk, Acc *sh)
 {
+  if (chunk > 0 && (int64_t)chunk * kRedThreads >= n) return;  // empty; chunk 0 always stores the scalars
   const Acc rz = reduce_partials(part2, 2, sh);
   const Acc rr = reduce_partials(part2 + 1, 2, sh);
   const Acc beta = use_beta ? rz / scal[cur] : Acc(0);
