@@ -188,3 +188,33 @@ def test_apply_argument_errors(dg):
     with pytest.raises(dg.DGError):
         op.apply(x.float(), torch.zeros(op.n_dofs, dtype=torch.float32, device="cuda"))  # F32 not enabled
     op.close()
+
+
+def test_apply_largest_size(dg, orc):
+    """The largest problem the library accepts: 256^3 affine cells at k=4,
+    2,097,152,000 DoFs (just under 2^31).  Offsets of the last cells pass
+    2^31 elements and 16 GB, so this checks the 64-bit address arithmetic;
+    sampled cells (corners, the very last cells, random) against the oracle."""
+    import torch
+    N, k = 256, 4
+    n3 = (k + 1) ** 3
+    op = dg.Operator(N, k, precisions=dg.PREC_F64)
+    nd = op.n_dofs
+    assert nd == N ** 3 * n3 and nd < 2 ** 31
+    g = torch.Generator(device="cuda")
+    g.manual_seed(256)
+    x = torch.rand(nd, dtype=torch.float64, device="cuda", generator=g) * 2.0 - 1.0
+    y = torch.full_like(x, float("nan"))
+    op.apply(x, y)
+    cells = np.unique(np.concatenate([synth.sample_cells(N, 200, seed=256, n_boundary=40),
+                                      np.arange(N ** 3 - 8, N ** 3)]))
+    rows = torch.from_numpy(cells).cuda()
+    got = y.view(-1, n3).index_select(0, rows).cpu().numpy()
+    assert np.isfinite(got).all()
+    src = x.cpu().numpy()
+    del y
+    ref = orc.apply_cells(orc.problem(N, k), src, cells)
+    assert _rel(got, ref) <= TOL64
+    del x, src
+    op.close()
+    torch.cuda.empty_cache()
