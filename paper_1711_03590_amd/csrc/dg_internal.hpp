@@ -109,7 +109,16 @@ hipError_t launch_apply(const dg_op *op, const void *src, void *dst, bool f32, h
 template <int N>
 hipError_t launch_diag(const dg_op *op, void *diag64, void *diag32, hipStream_t s);
 
+template <int N>
+hipError_t launch_apply_dot(const dg_op *op, const void *src, void *dst, bool f32, void *part, hipStream_t s);
+template <int N>
+int apply_workgroups(const dg_op *op);
+
 hipError_t launch_apply_any(const dg_op *op, const void *src, void *dst, bool f32, hipStream_t s);
+// dst = A src for the SIPG operator and the workgroup shares of src.dst in
+// part (apply_workgroups_any(op) entries, see DotOut)
+hipError_t launch_apply_dot_any(const dg_op *op, const void *src, void *dst, bool f32, void *part, hipStream_t s);
+int apply_workgroups_any(const dg_op *op);
 hipError_t launch_diag_any(const dg_op *op, void *diag64, void *diag32, hipStream_t s);
 
 }  // namespace dgk

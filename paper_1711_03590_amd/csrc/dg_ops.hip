@@ -19,7 +19,10 @@ namespace dgk {
 #define DG_EXTERN_N(N)                                                                  \
   extern template hipError_t launch_apply<N>(const dg_op *, const void *, void *, bool, \
                                              hipStream_t);                              \
-  extern template hipError_t launch_diag<N>(const dg_op *, void *, void *, hipStream_t);
+  extern template hipError_t launch_diag<N>(const dg_op *, void *, void *, hipStream_t);        \
+  extern template hipError_t launch_apply_dot<N>(const dg_op *, const void *, void *, bool,    \
+                                                 void *, hipStream_t);                          \
+  extern template int apply_workgroups<N>(const dg_op *);
 DG_EXTERN_N(2)
 DG_EXTERN_N(3)
 DG_EXTERN_N(4)
@@ -74,6 +77,36 @@ hipError_t launch_apply_any(const dg_op *op, const void *src, void *dst, bool f3
     case 8: return launch_apply<8>(op, src, dst, f32, s);
     case 9: return launch_apply<9>(op, src, dst, f32, s);
     default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_apply_dot_any(const dg_op *op, const void *src, void *dst, bool f32, void *part, hipStream_t s)
+{
+  switch (op->n) {
+    case 2: return launch_apply_dot<2>(op, src, dst, f32, part, s);
+    case 3: return launch_apply_dot<3>(op, src, dst, f32, part, s);
+    case 4: return launch_apply_dot<4>(op, src, dst, f32, part, s);
+    case 5: return launch_apply_dot<5>(op, src, dst, f32, part, s);
+    case 6: return launch_apply_dot<6>(op, src, dst, f32, part, s);
+    case 7: return launch_apply_dot<7>(op, src, dst, f32, part, s);
+    case 8: return launch_apply_dot<8>(op, src, dst, f32, part, s);
+    case 9: return launch_apply_dot<9>(op, src, dst, f32, part, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int apply_workgroups_any(const dg_op *op)
+{
+  switch (op->n) {
+    case 2: return apply_workgroups<2>(op);
+    case 3: return apply_workgroups<3>(op);
+    case 4: return apply_workgroups<4>(op);
+    case 5: return apply_workgroups<5>(op);
+    case 6: return apply_workgroups<6>(op);
+    case 7: return apply_workgroups<7>(op);
+    case 8: return apply_workgroups<8>(op);
+    case 9: return apply_workgroups<9>(op);
+    default: return 0;
   }
 }
 

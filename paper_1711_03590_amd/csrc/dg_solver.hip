@@ -5,7 +5,9 @@
 // Every reduction is deterministic: dot products are summed over a fixed
 // partition of the vector (kRedBlocks blocks, grid-stride), each block in a
 // fixed tree order, and the block partials are reduced in a fixed order by
-// every block that needs the result.  Scalars (alpha, beta) never leave the
+// every block that needs the result.  The product p.(A p) comes out of the
+// apply itself (per-workgroup shares, summed in a fixed order by a
+// one-workgroup kernel), which saves one pass over p and q per iteration.  Scalars (alpha, beta) never leave the
 // device; the host reads the residual norm back only every check_every
 // iterations, asynchronously into pinned memory.
 #include <hip/hip_runtime.h>
@@ -55,13 +57,33 @@ template <typename Real, typename Acc>
 struct PcgBuffers {
   Real *r = nullptr, *p = nullptr, *q = nullptr;
   Acc *part = nullptr;
-  bool alloc(Workspace &ws, int64_t n)
+  Real *wgpart = nullptr;     // per-workgroup shares of p.(A p)
+  int nwg = 0;
+  bool alloc(Workspace &ws, dg_op *op)
   {
+    const int64_t n = op->ndofs;
     r = static_cast<Real *>(ws.get(n * sizeof(Real)));
     p = static_cast<Real *>(ws.get(n * sizeof(Real)));
     q = static_cast<Real *>(ws.get(n * sizeof(Real)));
     part = static_cast<Acc *>(ws.get(3 * kRedBlocks * sizeof(Acc) + 4 * sizeof(Acc)));
-    return r && p && q && part;
+    nwg = apply_workgroups_any(op);
+    wgpart = static_cast<Real *>(ws.get((size_t)nwg * sizeof(Real)));
+    return r && p && q && part && wgpart;
+  }
+  // p.q partials: only entry 0 is written (the sum of the apply's shares),
+  // the rest stay zero, so the update kernels' fixed-order sum returns it
+  hipError_t clear(hipStream_t s) const
+  {
+    hipLaunchKernelGGL((fill_kernel<Acc>), dim3(1), dim3(kRedThreads), 0, s, part, Acc(0), (int64_t)kRedBlocks);
+    return hipGetLastError();
+  }
+  // q = A p and pq_part[0] = p.q
+  hipError_t apply_dot(dg_op *op, const Real *p, Real *q, hipStream_t s) const
+  {
+    hipError_t e = launch_apply_dot_any(op, p, q, sizeof(Real) == 4, wgpart, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((sum_shares_kernel<Acc>), dim3(1), dim3(kSumThreads), 0, s, wgpart, nwg, part);
+    return hipGetLastError();
   }
 };
 
@@ -96,6 +118,7 @@ dg_status pcg(dg_op *op, const Real *rhs, Real *x, bool x_zero, double tol_abs, 
   Acc *scal = part + 3 * kRedBlocks;      // rz[2] (ping-pong), rr, spare
   const Real *d = static_cast<const Real *>(op->diag[f32 ? 1 : 0]);
   const int grid = kRedBlocks;
+  DG_HIP(buf.clear(s));
   // r = rhs - A x
   if (x_zero) {
     hipLaunchKernelGGL((copy_kernel<Real>), dim3(grid), dim3(kRedThreads), 0, s, rhs, r, n);
@@ -122,8 +145,7 @@ dg_status pcg(dg_op *op, const Real *rhs, Real *x, bool x_zero, double tol_abs, 
   if (st != DG_OK) return st;
   if (!(rn > tol_abs)) done = true;
   while (!done && it < max_iter) {
-    DG_HIP(launch_apply_any(op, p, q, f32, s));
-    hipLaunchKernelGGL((dot_partial_kernel<Real, Acc>), dim3(grid), dim3(kRedThreads), 0, s, p, q, n, pq_part);
+    DG_HIP(buf.apply_dot(op, p, q, s));
     hipLaunchKernelGGL((cg_update_kernel<Real, Acc>), dim3(grid), dim3(kRedThreads), 0, s, x, r, p, q, d, n,
                        pq_part, scal, par, rz_part);
     hipLaunchKernelGGL((cg_pupdate_kernel<Real, Acc>), dim3(grid), dim3(kRedThreads), 0, s, p, r, d, n, rz_part,
@@ -144,8 +166,8 @@ dg_status pcg(dg_op *op, const Real *rhs, Real *x, bool x_zero, double tol_abs, 
 
 // FP32 Jacobi-PCG with reliable updates inside FP64 refinement: the FP32
 // recurrence runs on the relative system A e = r / ||b||; each time its
-// residual has dropped tenfold since the last refinement (checked every
-// check_every iterations), the FP32 correction is flushed into the FP64
+// residual has dropped by the factor delta since the last refinement
+// (checked every check_every iterations), the FP32 correction is flushed into the FP64
 // solution (x += ||b|| e), the FP64 residual b - A x is recomputed with an
 // FP64 apply and replaces the FP32 residual, and the search direction is
 // kept, so no Krylov information is lost at a refinement step.
@@ -180,13 +202,13 @@ dg_status pcg_reliable(dg_op *op, const double *b, double *x, double nb, double 
   if (rc != DG_OK) return rc;
   *rel_out = rel;
   if (rel <= tol) return DG_OK;
+  DG_HIP(buf.clear(s));
   DG_HIP(start_direction_async(n, e, r, p, d, buf.part, s));
   int par = 1;
   double rlast = rel;
   st.iters_outer = 1;
   for (int it = 1; it <= max_iter; ++it) {
-    DG_HIP(launch_apply_any(op, p, q, true, s));
-    hipLaunchKernelGGL((dot_partial_kernel<float, float>), dim3(grid), dim3(kRedThreads), 0, s, p, q, n, pq_part);
+    DG_HIP(buf.apply_dot(op, p, q, s));
     hipLaunchKernelGGL((cg_update_kernel<float, float>), dim3(grid), dim3(kRedThreads), 0, s, e, r, p, q, d, n,
                        pq_part, scal, par, rz_part);
     hipLaunchKernelGGL((cg_pupdate_kernel<float, float>), dim3(grid), dim3(kRedThreads), 0, s, p, r, d, n, rz_part,
@@ -284,7 +306,7 @@ extern "C" dg_status dg_cg_solve(dg_op *op, dg_vec b, dg_vec x, const dg_solve_p
     // FP64 Jacobi-PCG; restarted from the true residual if the recurrence
     // residual drifted below the tolerance first
     PcgBuffers<double, double> buf;
-    if (!buf.alloc(ws, n)) return fail(DG_ERR_OOM, "solver workspace allocation failed");
+    if (!buf.alloc(ws, op)) return fail(DG_ERR_OOM, "solver workspace allocation failed");
     for (int restart = 0; restart < 4; ++restart) {
       int it = 0;
       double rn = 0.0;
@@ -304,7 +326,7 @@ extern "C" dg_status dg_cg_solve(dg_op *op, dg_vec b, dg_vec x, const dg_solve_p
   } else if (prm->mode == 2) {
     float *e32 = static_cast<float *>(ws.get(n * sizeof(float)));
     PcgBuffers<float, float> buf;
-    if (!e32 || !buf.alloc(ws, n)) return fail(DG_ERR_OOM, "solver workspace allocation failed");
+    if (!e32 || !buf.alloc(ws, op)) return fail(DG_ERR_OOM, "solver workspace allocation failed");
     rc = pcg_reliable(op, bp, xp, nb, prm->rel_tol, prm->rel_tol_inner, prm->max_iter, prm->check_every, buf, e32,
                       r64, part, pin, s, st, &rel);
     if (rc == DG_OK) result = DG_OK;
@@ -314,7 +336,7 @@ extern "C" dg_status dg_cg_solve(dg_op *op, dg_vec b, dg_vec x, const dg_solve_p
     float *r32 = static_cast<float *>(ws.get(n * sizeof(float)));
     float *d32 = static_cast<float *>(ws.get(n * sizeof(float)));
     PcgBuffers<float, float> buf;
-    if (!r32 || !d32 || !buf.alloc(ws, n)) return fail(DG_ERR_OOM, "solver workspace allocation failed");
+    if (!r32 || !d32 || !buf.alloc(ws, op)) return fail(DG_ERR_OOM, "solver workspace allocation failed");
     for (int outer = 0; outer <= prm->max_outer; ++outer) {
       if ((rc = true_residual(&rel)) != DG_OK) return rc;
       if (rel <= prm->rel_tol) {

@@ -9,4 +9,6 @@
 namespace dgk {
 template hipError_t launch_apply<DG_N>(const dg_op *, const void *, void *, bool, hipStream_t);
 template hipError_t launch_diag<DG_N>(const dg_op *, void *, void *, hipStream_t);
+template hipError_t launch_apply_dot<DG_N>(const dg_op *, const void *, void *, bool, void *, hipStream_t);
+template int apply_workgroups<DG_N>(const dg_op *);
 }  // namespace dgk

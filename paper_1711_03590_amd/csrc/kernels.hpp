@@ -495,11 +495,38 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
   }
 }
 
+// Optional output of the solver's product p.(A p) computed inside the apply:
+// part[blk] receives each workgroup's share (a fixed-order sum over its
+// threads); the caller sums the shares in workgroup order afterwards.
+template <typename Real>
+struct DotOut {
+  Real *part = nullptr;
+};
+
+// fixed-order tree sum over the TPB threads of a workgroup (sh: TPB values)
+template <int TPB, typename Real>
+__device__ __forceinline__ Real wg_sum(Real v, Real *sh)
+{
+  static_assert((TPB & (TPB - 1)) == 0, "power-of-two workgroups");
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  const Real r = sh[0];
+  __syncthreads();
+  return r;
+}
+
 // The fused pass over the cells of one batch (cells blk*B .. blk*B+B-1) by
 // a workgroup of TPB threads; smem holds B * (2 N^3 + WSZ) values.
-template <int N, typename Real, int GK, int TPB>
+template <int N, typename Real, int GK, int TPB, bool DOT = false>
 __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *__restrict__ src,
-                                            Real *__restrict__ dst, int blk, Real *smem)
+                                            Real *__restrict__ dst, int blk, Real *smem,
+                                            const DotOut<Real> &dot = DotOut<Real>{})
 {
   using BK = Blocking<N, TPB>;
   constexpr int N2 = BK::N2, N3 = BK::N3, B = BK::B, NT = BK::NT, WSZ = BK::WSZ;
@@ -684,15 +711,29 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
   __syncthreads();
   const Real *Rall = smem + B * N3;
   for (int i = t; i < nhere * N3; i += TPB) dst[g0 + i] = Rall[i];
+  if constexpr (DOT) {
+    // this workgroup's share of src.(A src): the gathered values gv are
+    // src at the same indices the write loop above visits
+    Real v = Real(0);
+#pragma unroll
+    for (int j = 0; j < GI; ++j) {
+      const int i = t + j * TPB;
+      if (i < nhere * N3) v += gv[j] * Rall[i];
+    }
+    static_assert(TPB <= B * N3, "Q holds the workgroup sum");
+    const Real wsum = wg_sum<TPB>(v, smem);   // Q is free after the last sweep
+    if (t == 0) dot.part[blk] = wsum;
+  }
 }
 
-template <int N, typename Real, int GK>
+template <int N, typename Real, int GK, bool DOT = false>
 __global__ void __launch_bounds__(Blocking<N>::TPB, (Occupancy<N, Real>::value))
-sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__restrict__ dst)
+sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__restrict__ dst,
+                  const DotOut<Real> dot = DotOut<Real>{})
 {
   using BK = Blocking<N>;
   __shared__ Real smem[BK::SMEM];
-  apply_batch<N, Real, GK, BK::TPB>(op, src, dst, xcd_remap(blockIdx.x, gridDim.x), smem);
+  apply_batch<N, Real, GK, BK::TPB, DOT>(op, src, dst, xcd_remap(blockIdx.x, gridDim.x), smem, dot);
 }
 
 // ---------------------------------------------------------------------------
@@ -887,6 +928,37 @@ hipError_t launch_apply(const dg_op *op, const void *src, void *dst, bool f32, h
     }
   }
   return hipGetLastError();
+}
+
+// the SIPG apply that also writes the workgroup shares of src.(A src) (FP32
+// or FP64 as the vectors) into part, apply_workgroups(op) entries
+template <int N>
+hipError_t launch_apply_dot(const dg_op *op, const void *src, void *dst, bool f32, void *part, hipStream_t s)
+{
+  using BK = Blocking<N>;
+  const int grid = (int)((op->ncells + BK::B - 1) / BK::B);
+  if (grid == 0) return hipSuccess;
+  auto go = [&](auto zero, const auto &view) {
+    using Real = decltype(zero);
+    const Real *x = static_cast<const Real *>(src);
+    Real *y = static_cast<Real *>(dst);
+    DotOut<Real> d{static_cast<Real *>(part)};
+    switch (op->gk) {
+      case CURVED: hipLaunchKernelGGL((sipg_apply_kernel<N, Real, CURVED, true>), dim3(grid), dim3(BK::TPB), 0, s, view, x, y, d); break;
+      case CURVED_MERGED: hipLaunchKernelGGL((sipg_apply_kernel<N, Real, CURVED_MERGED, true>), dim3(grid), dim3(BK::TPB), 0, s, view, x, y, d); break;
+      case AFFINE_VAR: hipLaunchKernelGGL((sipg_apply_kernel<N, Real, AFFINE_VAR, true>), dim3(grid), dim3(BK::TPB), 0, s, view, x, y, d); break;
+      default: hipLaunchKernelGGL((sipg_apply_kernel<N, Real, AFFINE_CONST, true>), dim3(grid), dim3(BK::TPB), 0, s, view, x, y, d); break;
+    }
+  };
+  if (f32) go(0.0f, op->v32);
+  else go(0.0, op->v64);
+  return hipGetLastError();
+}
+
+template <int N>
+int apply_workgroups(const dg_op *op)
+{
+  return (int)((op->ncells + Blocking<N>::B - 1) / Blocking<N>::B);
 }
 
 template <int N>

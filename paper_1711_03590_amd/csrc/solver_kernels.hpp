@@ -88,6 +88,34 @@ __global__ void __launch_bounds__(kRedThreads) finalize_kernel(const Acc *__rest
   if (threadIdx.x == 0) out[0] = v;
 }
 
+// out[0] = the sum of part[0 .. count) in a fixed order: thread t sums the
+// entries t, t + T, t + 2T, ... (eight loads issued before their adds), then
+// a fixed tree over the T = 1024 threads of the one workgroup
+constexpr int kSumThreads = 1024;
+template <typename Acc>
+__global__ void __launch_bounds__(kSumThreads) sum_shares_kernel(const Acc *__restrict__ part, int count, Acc *out)
+{
+  __shared__ Acc sh[kSumThreads];
+  const int t = threadIdx.x;
+  Acc v = Acc(0);
+  int i = t;
+  for (; i + 7 * kSumThreads < count; i += 8 * kSumThreads) {
+    Acc a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = part[i + u * kSumThreads];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += a[u];
+  }
+  for (; i < count; i += kSumThreads) v += part[i];
+  sh[t] = v;
+  __syncthreads();
+  for (int w = kSumThreads / 2; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  if (t == 0) out[0] = sh[0];
+}
+
 template <typename Real>
 __global__ void copy_kernel(const Real *__restrict__ a, Real *__restrict__ b, int64_t n)
 {
