@@ -3,7 +3,7 @@
 
 Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It wraps ``liboracle.so`` (built from
-``oracle.c`` with gcc, see ``build.py``), which evaluates y = A u for the
+``oracle.c`` with gcc, see ``buildlib.py``), which evaluates y = A u for the
 symmetric interior penalty form of Sec. 2, Eq. (2) of Kronbichler & Kormann
 (arXiv 1711.03590) by plain point-by-point quadrature: no sum factorisation,
 no shared code with the GPU library.
@@ -86,8 +86,8 @@ def problem(ncell, degree, *, curved=False, amplitude=0.05, variable_coef=False,
 
 
 def build(force: bool = False) -> str:
-    from . import build as _b
-    return _b.build(force=force)
+    from . import buildlib
+    return buildlib.build(force=force)
 
 
 def lib():

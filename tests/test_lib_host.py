@@ -132,3 +132,10 @@ def test_bad_velocity_rejected(dg):
     st = dg.lib().dg_footprint_advection(ctypes.byref(m), 3, ctypes.byref(g), ctypes.byref(v), dg.PREC_F64,
                                          ctypes.byref(out))
     assert st == dg.DG_ERR_ARG
+
+
+def test_build_entry_compiles_the_oracle():
+    import os
+    import oracle
+    path = oracle.build(force=True)
+    assert os.path.exists(path) and path.endswith("liboracle.so")
