@@ -18,6 +18,10 @@ Parity status per function (what pins it is in tests/test_oracle_*.py):
   diag_cells                    pinned: equals the diagonal of the brute-force matrix
   face_point / volume           pinned: boundary area element, mapped volume
   rhs / errors                  pinned: GLL-weight closed form, convergence order
+  basis1d("hermite") and apply  pinned: the defining functionals, the cubic Hermite
+  with basis="hermite"          closed form, reproduction of polynomials, mirror
+                                symmetry; block rows equal the cell-wise change of
+                                basis of the nodal operator's; convergence order
   apply with op="advection"     pinned: constants map to the inflow flux alone and
                                 the energy identity u^T A u = upwind jump terms
                                 (affine, exact quadrature), convergence order of
@@ -39,6 +43,7 @@ MAP_AFFINE, MAP_SINE = 0, 1
 COEF_CONST, COEF_SINCOS = 0, 1
 OP_SIPG, OP_ADVECTION = 0, 1
 VEL_CONST, VEL_ROTATION = 0, 1
+BASIS_GLL, BASIS_HERMITE = 0, 1
 
 
 class Problem(ctypes.Structure):
@@ -55,14 +60,19 @@ class Problem(ctypes.Structure):
         ("op", ctypes.c_int32),
         ("vel", ctypes.c_int32),
         ("vel_value", ctypes.c_double * 3),
+        ("basis", ctypes.c_int32),
     ]
 
 
 def problem(ncell, degree, *, curved=False, amplitude=0.05, variable_coef=False,
             coef_value=1.0, bc=(DIRICHLET,) * 6, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
-            op="sipg", velocity="rotation"):
+            op="sipg", velocity="rotation", basis="gll"):
     """op="sipg" (Sec. 2 Eq. (2)) or "advection" (Eq. (1)); for advection the
-    velocity is "rotation" (1/2 - y, x - 1/2, 1/4) or a constant 3-vector."""
+    velocity is "rotation" (1/2 - y, x - 1/2, 1/4) or a constant 3-vector.
+    basis="gll" (Lagrange on the Gauss-Lobatto points) or "hermite" (the
+    Hermite-like basis, degree >= 3)."""
+    if basis not in ("gll", "hermite"):
+        raise ValueError("basis is 'gll' or 'hermite'")
     if isinstance(ncell, int):
         ncell = (ncell, ncell, ncell)
     p = Problem()
@@ -76,6 +86,7 @@ def problem(ncell, degree, *, curved=False, amplitude=0.05, variable_coef=False,
     p.coef = COEF_SINCOS if variable_coef else COEF_CONST
     p.coef_value = coef_value
     p.op = OP_ADVECTION if op == "advection" else OP_SIPG
+    p.basis = BASIS_HERMITE if basis == "hermite" else BASIS_GLL
     if isinstance(velocity, str):
         p.vel = VEL_ROTATION
         p.vel_value[:] = [0.0, 0.0, 0.0]
@@ -102,6 +113,7 @@ def lib():
         L.orc_gauss.argtypes = [ctypes.c_int, dp, dp]
         L.orc_gll.argtypes = [ctypes.c_int, dp]
         L.orc_lagrange.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_double, dp, dp]
+        L.orc_basis1d.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp]
         L.orc_n_dofs.argtypes = [pp]
         L.orc_n_dofs.restype = ctypes.c_int64
         L.orc_apply.argtypes = [pp, dp, dp]
@@ -154,6 +166,15 @@ def lagrange(nodes, j, xi):
     d = ctypes.c_double()
     _check(lib().orc_lagrange(len(nodes), _dp(nodes), j, float(xi), ctypes.byref(v), ctypes.byref(d)),
            "lagrange")
+    return v.value, d.value
+
+
+def basis1d(n, basis, j, xi):
+    """Value and derivative at xi of 1D basis function j of n ("gll" or "hermite")."""
+    v = ctypes.c_double()
+    d = ctypes.c_double()
+    _check(lib().orc_basis1d(n, BASIS_HERMITE if basis == "hermite" else BASIS_GLL, j, float(xi),
+                             ctypes.byref(v), ctypes.byref(d)), "basis1d")
     return v.value, d.value
 
 

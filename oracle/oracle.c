@@ -39,6 +39,18 @@
  *     (Nanson's formula ds = det J |J^{-T} e| w); the neighbour's gradient uses
  *     the neighbour's own Jacobian at the same physical point.
  *   - homogeneous Neumann faces contribute nothing.
+ *   - Hermite-like basis (problem field basis = 1, degree k >= 3): the paper
+ *     asks only that a face value and a face derivative each need at most two
+ *     coefficients per normal line (Sec. 3, the face interpolation kernel;
+ *     Sec. 4.4).  Reading: the basis dual to the k+1 functionals
+ *       u(0), x_1 u'(0), u(x_2), ..., u(x_{k-2}), -x_1 u'(1), u(1)
+ *     with x_m the Gauss-Lobatto points (x_1 = 1 - x_{k-1} their first
+ *     interior spacing, which scales the derivative functionals like a
+ *     value).  Only phi_0 is non-zero at 0 and only phi_1 has a slope there
+ *     (mirrored at 1), the interior functions vanish with their slope at both
+ *     ends, and phi_{k-j}(x) = phi_j(1-x).  It spans the same polynomials as
+ *     the nodal basis, so the discrete solution is the same; A changes by the
+ *     cell-wise change of basis.
  *
  * The same library also evaluates the second operator of the paper, the DG
  * discretisation of stationary advection with the local Lax-Friedrichs
@@ -84,6 +96,7 @@ typedef struct {
   int32_t op;         /* 0 = SIPG Laplacian, 1 = advection with upwind flux */
   int32_t vel;        /* advection velocity: 0 = constant vel_value, 1 = (1/2 - y, x - 1/2, 1/4) */
   double vel_value[3];
+  int32_t basis;      /* 0 = Lagrange on the Gauss-Lobatto points, 1 = Hermite-like (k >= 3) */
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -175,6 +188,63 @@ int orc_lagrange(int n, const double *nodes, int j, double xi, double *val, doub
   return ORC_OK;
 }
 
+/* The Hermite-like basis written in the Lagrange basis on the n Gauss-Lobatto
+ * points x: phi_j = sum_i T[i*n + j] l_i, i.e. T[i*n + j] = phi_j(x_i).  The
+ * value functionals at x_0, x_2..x_{n-3}, x_{n-1} pick T's rows directly
+ * (T[i*n + j] = delta_ij there); the two derivative functionals leave the
+ * rows i = 1 and i = n-2 as the unknowns of a 2x2 system per j, solved by
+ * Cramer's rule. */
+static int hermite_table(int n, const double *x, double *T)
+{
+  if (n < 4 || n > ORC_MAXN) return ORC_ERR_ARG;
+  const int a = 1, b = n - 2;
+  const double s = x[1];
+  /* slopes at 0 and at 1 of the two free Lagrange polynomials */
+  const double m00 = lag_der(n, x, a, 0.0), m01 = lag_der(n, x, b, 0.0);
+  const double m10 = lag_der(n, x, a, 1.0), m11 = lag_der(n, x, b, 1.0);
+  const double det = m00 * m11 - m01 * m10;
+  if (fabs(det) < 1e-300) return ORC_ERR_ARG;
+  for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < n; ++i) T[i * n + j] = 0.0;
+    /* required slopes phi_j'(0) = r0 and phi_j'(1) = r1, minus what the
+     * fixed nodal values already give */
+    double r0 = (j == a) ? 1.0 / s : 0.0;
+    double r1 = (j == b) ? -1.0 / s : 0.0;
+    if (j != a && j != b) {
+      T[j * n + j] = 1.0;
+      r0 -= lag_der(n, x, j, 0.0);
+      r1 -= lag_der(n, x, j, 1.0);
+    }
+    T[a * n + j] = (r0 * m11 - m01 * r1) / det;
+    T[b * n + j] = (m00 * r1 - r0 * m10) / det;
+  }
+  return ORC_OK;
+}
+
+/* 1D basis function j of the given kind (0 Lagrange on Gauss-Lobatto points,
+ * 1 Hermite-like) with n functions, value and derivative at xi. */
+int orc_basis1d(int n, int basis, int j, double xi, double *val, double *der)
+{
+  double x[ORC_MAXN], T[ORC_MAXN * ORC_MAXN];
+  if (n < 2 || n > ORC_MAXN || j < 0 || j >= n || (basis != 0 && basis != 1)) return ORC_ERR_ARG;
+  orc_gll(n, x);
+  if (basis == 0) {
+    *val = lag_val(n, x, j, xi);
+    *der = lag_der(n, x, j, xi);
+    return ORC_OK;
+  }
+  int rc = hermite_table(n, x, T);
+  if (rc) return rc;
+  double v = 0.0, d = 0.0;
+  for (int i = 0; i < n; ++i) {
+    v += T[i * n + j] * lag_val(n, x, i, xi);
+    d += T[i * n + j] * lag_der(n, x, i, xi);
+  }
+  *val = v;
+  *der = d;
+  return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Problem context: 1D rules and basis tables at the reference points        */
 /* ------------------------------------------------------------------------ */
@@ -184,6 +254,7 @@ typedef struct {
   int n, n3;
   double h[3];
   double gll[ORC_MAXN];
+  double herm[ORC_MAXN * ORC_MAXN]; /* Hermite-like basis in the Lagrange one (basis 1) */
   double gx[ORC_MAXN], gw[ORC_MAXN];
   /* cell tables at the n^3 Gauss points q = q1 + n q2 + n^2 q3:
    * val[q*n3 + i], grad[(q*n3 + i)*3 + d] */
@@ -208,15 +279,24 @@ static void tangential_axes(int a, int *t1, int *t2)
 }
 
 /* phi_i and its reference gradient at reference point xi (tensor product of
- * 1D Lagrange polynomials on the Gauss-Lobatto nodes). */
+ * 1D Lagrange polynomials on the Gauss-Lobatto nodes, or of the Hermite-like
+ * functions built from them). */
 static void basis_at(const orc_ctx *c, const double xi[3], int i, double *v, double g[3])
 {
   int n = c->n;
   int id[3] = {i % n, (i / n) % n, i / (n * n)};
   double l[3], dl[3];
   for (int d = 0; d < 3; ++d) {
-    l[d] = lag_val(n, c->gll, id[d], xi[d]);
-    dl[d] = lag_der(n, c->gll, id[d], xi[d]);
+    if (c->P.basis == 1) {
+      l[d] = dl[d] = 0.0;
+      for (int m = 0; m < n; ++m) {
+        l[d] += c->herm[m * n + id[d]] * lag_val(n, c->gll, m, xi[d]);
+        dl[d] += c->herm[m * n + id[d]] * lag_der(n, c->gll, m, xi[d]);
+      }
+    } else {
+      l[d] = lag_val(n, c->gll, id[d], xi[d]);
+      dl[d] = lag_der(n, c->gll, id[d], xi[d]);
+    }
   }
   *v = l[0] * l[1] * l[2];
   g[0] = dl[0] * l[1] * l[2];
@@ -248,10 +328,12 @@ static int ctx_init(orc_ctx *c, const orc_problem *P)
   if (P->coef != 0 && P->coef != 1) return ORC_ERR_ARG;
   if (P->op != 0 && P->op != 1) return ORC_ERR_ARG;
   if (P->vel != 0 && P->vel != 1) return ORC_ERR_ARG;
+  if (P->basis != 0 && (P->basis != 1 || P->degree < 3)) return ORC_ERR_ARG;
   int n = P->degree + 1, n2 = n * n, n3 = n2 * n;
   c->n = n;
   c->n3 = n3;
   orc_gll(n, c->gll);
+  if (P->basis == 1 && hermite_table(n, c->gll, c->herm) != ORC_OK) return ORC_ERR_ARG;
   orc_gauss(n, c->gx, c->gw);
   c->val = malloc(sizeof(double) * (size_t)n3 * n3);
   c->grad = malloc(sizeof(double) * (size_t)n3 * n3 * 3);
