@@ -207,9 +207,10 @@ def main():
 
     del flush
     hbm = measure_hbm(torch)
-    variants = merged = advection = None
+    variants = merged = advection = hermite = None
     if args.variants:
         merged = bench_merged(dg, torch, synth, N, k, args.steps, args.warmup, res)
+        hermite = bench_hermite(dg, torch, synth, N, k, args.steps, args.warmup, res)
         advection = bench_advection(dg, torch, synth, N, k, args.steps, args.warmup)
         variants = bench_variants(dg, torch, synth, k)
 
@@ -265,6 +266,8 @@ def main():
                         "per_launch_us": r["per_launch_us"], "speedup_vs_fp64": r["dofs"] / head["dofs"]}
     if merged:
         line["merged_geometry"] = merged
+    if hermite:
+        line["hermite_basis"] = hermite
     if advection:
         line["advection"] = advection
     if variants:
@@ -329,6 +332,35 @@ def bench_merged(dg, torch, synth, ncell, k, steps, warmup, g3):
             out[prec]["speedup_vs_g3"] = out[prec]["dofs_per_s"] / g3[prec]["dofs"]
         del x, y
     op.close()
+    return out
+
+
+def bench_hermite(dg, torch, synth, ncell, k, steps, warmup, g3):
+    """The headline workload in the Hermite-like basis (a neighbour's face
+    data from two of its N coefficients per normal line), with the stored
+    Jacobians (G3) and with the merged coefficient (G4).  Same bytes per DoF
+    as the nodal runs; a different, equivalent operator."""
+    out = {"workload": f"{ncell}^3 sine-curved, k={k}, Hermite-like basis"}
+    for geo, merged in (("G3", False), ("G4", True)):
+        op = dg.Operator(ncell, k, curved=True, amplitude=synth.AMPLITUDE, merged=merged, basis="hermite")
+        nd = op.n_dofs
+        src = synth.src_vector(nd, synth.seed_for(2, k))
+        out[geo] = {}
+        for prec in ("f64", "f32"):
+            dt = torch.float64 if prec == "f64" else torch.float32
+            x = torch.from_numpy(src).to(dtype=dt, device="cuda")
+            y = torch.empty_like(x)
+            ms = time_apply(op, x, y, steps, warmup, torch)
+            bpd = algorithmic_bytes_per_dof(ncell, k, 8 if prec == "f64" else 4,
+                                            "curved-merged" if merged else "curved")
+            gbs = bpd * nd / (ms * 1e-3) / 1e9
+            r = {"dofs_per_s": nd / (ms * 1e-3), "us": ms * 1e3, "algorithmic_bytes_per_dof": bpd,
+                 "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+            if geo == "G3" and prec in g3:
+                r["speedup_vs_nodal"] = r["dofs_per_s"] / g3[prec]["dofs"]
+            out[geo][prec] = r
+            del x, y
+        op.close()
     return out
 
 

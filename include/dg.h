@@ -127,6 +127,33 @@ dg_status dg_setup(const dg_mesh *mesh, int degree, const dg_geometry *geom,
                    const dg_coefficient *coef, unsigned precisions, const dg_allocator *alloc,
                    void *stream, dg_op **out);
 
+/* Polynomial basis of the SIPG operator.  Both span the tensor-product
+ * polynomials of degree k on each cell, so the discrete solution is the same;
+ * A changes by the cell-wise change of basis.
+ * DG_BASIS_NODAL: Lagrange polynomials on the k+1 Gauss-Lobatto points (the
+ *   dg_setup default; DoF = value at a node).
+ * DG_BASIS_HERMITE: a Hermite-like basis (k >= 3) in the sense of Sec. 3 and
+ *   Sec. 4.4: the 1D functions are dual to the functionals
+ *   u(0), s u'(0), u(x_2), ..., u(x_{k-2}), -s u'(1), u(1) with x_m the
+ *   Gauss-Lobatto points and s = x_1, so that a face value needs one and a
+ *   face derivative one more coefficient per normal line (2 (k+1)^2 of a
+ *   neighbour's (k+1)^3 per face). */
+typedef enum { DG_BASIS_NODAL = 0, DG_BASIS_HERMITE = 1 } dg_basis;
+
+/* dg_setup in the given basis.  DG_ERR_ARG for an unknown basis or
+ * DG_BASIS_HERMITE below degree 3.  Every call that takes the op (apply,
+ * diagonal, right-hand side, error, CG) works in that basis; dg_batch_admit
+ * returns DG_ERR_UNSUPPORTED for a Hermite op. */
+dg_status dg_setup_basis(const dg_mesh *mesh, int degree, dg_basis basis, const dg_geometry *geom,
+                         const dg_coefficient *coef, unsigned precisions, const dg_allocator *alloc, void *stream,
+                         dg_op **out);
+
+/* The 1D tables of a basis as the kernels use them, for degree k (n = k+1),
+ * written row-major into out: S[q][j] = phi_j(g_q) and D[q][j] = phi_j'(g_q)
+ * at the n Gauss points g_q (n*n each), then phi_j(0), phi_j(1), phi_j'(0),
+ * phi_j'(1) (n each).  len >= 2 n^2 + 4 n.  Pure host computation. */
+dg_status dg_basis_tables(int degree, dg_basis basis, double *out, size_t len);
+
 /* Transport velocity of the advection operator (Sec. 2, Eq. (1)).
  * DG_VEL_CONST: c = value (a constant vector).
  * DG_VEL_ROTATION: c(x) = (1/2 - y, x - 1/2, 1/4), a divergence-free

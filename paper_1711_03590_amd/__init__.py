@@ -21,6 +21,7 @@ MAP_AFFINE, MAP_SINE = 0, 1
 STORE_JACOBIAN, STORE_MERGED = 0, 1
 COEF_CONST, COEF_SINCOS = 0, 1
 PREC_F64, PREC_F32 = 1, 2
+BASIS_NODAL, BASIS_HERMITE = 0, 1
 
 
 class DGError(RuntimeError):
@@ -96,6 +97,11 @@ _SIGS = [
     ("dg_setup", ctypes.c_int, [ctypes.POINTER(Mesh), ctypes.c_int, ctypes.POINTER(Geometry),
                                 ctypes.POINTER(Coefficient), ctypes.c_uint, ctypes.POINTER(Allocator), _P,
                                 ctypes.POINTER(_P)]),
+    ("dg_setup_basis", ctypes.c_int, [ctypes.POINTER(Mesh), ctypes.c_int, ctypes.c_int, ctypes.POINTER(Geometry),
+                                      ctypes.POINTER(Coefficient), ctypes.c_uint, ctypes.POINTER(Allocator), _P,
+                                      ctypes.POINTER(_P)]),
+    ("dg_basis_tables", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.c_size_t]),
     ("dg_footprint_advection", ctypes.c_int, [ctypes.POINTER(Mesh), ctypes.c_int, ctypes.POINTER(Geometry),
                                               ctypes.POINTER(Velocity), ctypes.c_uint,
                                               ctypes.POINTER(ctypes.c_size_t)]),
@@ -155,6 +161,25 @@ def tables(degree):
     check(lib().dg_tables(degree, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size))
     return {"gx": out[:n], "gw": out[n:2 * n], "lx": out[2 * n:3 * n],
             "S": out[3 * n:3 * n + n * n].reshape(n, n), "Dco": out[3 * n + n * n:].reshape(n, n)}
+
+
+def _basis(basis):
+    if basis not in ("nodal", "hermite"):
+        raise ValueError("basis must be 'nodal' or 'hermite'")
+    return BASIS_HERMITE if basis == "hermite" else BASIS_NODAL
+
+
+def basis_tables(degree, basis="nodal"):
+    """The compiled-in 1D basis tables (host only): S and D at the Gauss
+    points, and values and slopes at the ends (V0, V1, F0, F1)."""
+    import numpy as np
+    n = degree + 1
+    out = np.zeros(2 * n * n + 4 * n)
+    check(lib().dg_basis_tables(degree, _basis(basis), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                out.size))
+    o = 2 * n * n
+    return {"S": out[:n * n].reshape(n, n), "D": out[n * n:o].reshape(n, n), "V0": out[o:o + n],
+            "V1": out[o + n:o + 2 * n], "F0": out[o + 2 * n:o + 3 * n], "F1": out[o + 3 * n:o + 4 * n]}
 
 
 def make_mesh(ncell, bc=(DIRICHLET,) * 6, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
@@ -237,11 +262,13 @@ class TorchAllocator:
 
 
 class Operator:
-    """One SIPG operator (mesh, degree, geometry, coefficient) resident on the GPU."""
+    """One SIPG operator (mesh, degree, geometry, coefficient, basis) resident on the GPU.
+    basis: "nodal" (Lagrange on the Gauss-Lobatto points) or "hermite" (the
+    Hermite-like basis, degree >= 3)."""
 
     def __init__(self, ncell, degree, *, curved=False, amplitude=0.05, variable_coef=False, coef_value=1.0,
                  bc=(DIRICHLET,) * 6, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
-                 precisions=PREC_F64 | PREC_F32, torch_alloc=True, stream=None, merged=False):
+                 precisions=PREC_F64 | PREC_F32, torch_alloc=True, stream=None, merged=False, basis="nodal"):
         self._h = None
         self.degree = degree
         self.mesh = make_mesh(ncell, bc, lo, hi)
@@ -250,13 +277,19 @@ class Operator:
         self.merged = merged and curved
         self.variable_coef = variable_coef
         self.precisions = precisions
+        self.basis = basis
+        b = _basis(basis)
         self._alloc = TorchAllocator() if torch_alloc else None
         g = Geometry(MAP_SINE if curved else MAP_AFFINE, amplitude, STORE_MERGED if merged else STORE_JACOBIAN)
         c = Coefficient(COEF_SINCOS if variable_coef else COEF_CONST, coef_value)
         h = ctypes.c_void_p()
-        check(lib().dg_setup(ctypes.byref(self.mesh), degree, ctypes.byref(g), ctypes.byref(c), precisions,
-                             ctypes.byref(self._alloc.struct) if self._alloc else None, _stream(stream),
-                             ctypes.byref(h)))
+        alloc = ctypes.byref(self._alloc.struct) if self._alloc else None
+        if b == BASIS_NODAL:
+            check(lib().dg_setup(ctypes.byref(self.mesh), degree, ctypes.byref(g), ctypes.byref(c), precisions,
+                                 alloc, _stream(stream), ctypes.byref(h)))
+        else:
+            check(lib().dg_setup_basis(ctypes.byref(self.mesh), degree, b, ctypes.byref(g), ctypes.byref(c),
+                                       precisions, alloc, _stream(stream), ctypes.byref(h)))
         self._h = h
 
     @property

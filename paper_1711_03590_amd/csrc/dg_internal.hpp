@@ -70,6 +70,7 @@ struct dg_op {
   dg_geometry geom;
   dg_coefficient coef;
   dg_velocity vel{};         // advection ops only
+  int basis = 0;             // SIPG ops: DG_BASIS_NODAL or DG_BASIS_HERMITE
   unsigned precisions = 0;
   int gk = 0;
   int64_t ncells = 0, ndofs = 0, nfaces[3] = {0, 0, 0};

@@ -344,12 +344,13 @@ __device__ __forceinline__ double forcing(const GeoArgs &g, const double x[3], d
 }
 
 // one workgroup per cell: f det J w at the Gauss points into LDS, then
-// b = (S^T x S^T x S^T) of it
-template <int N>
+// b = (S^T x S^T x S^T) of it, S of the op's basis BS
+template <int N, int BS>
 __global__ void __launch_bounds__(1024) rhs_kernel(const GeoArgs g, double *__restrict__ b)
 {
   constexpr int N2 = N * N, N3 = N2 * N;
   constexpr const auto &T = kTab<N>;
+  constexpr const auto &BT = kBasis<N, BS>;
   __shared__ double F[N3];
   const int64_t cell = blockIdx.x;
   const int t = threadIdx.x;
@@ -368,26 +369,28 @@ __global__ void __launch_bounds__(1024) rhs_kernel(const GeoArgs g, double *__re
   double acc = 0.0;
   for (int q = 0; q < N3; ++q) {
     const int q1 = q % N, q2 = (q / N) % N, q3 = q / N2;
-    acc += T.S[q1][id[0]] * T.S[q2][id[1]] * T.S[q3][id[2]] * F[q];
+    acc += BT.S[q1][id[0]] * BT.S[q2][id[1]] * BT.S[q3][id[2]] * F[q];
   }
   b[cell * N3 + t] = acc;
 }
 
-// error integrals with M points per direction; per-cell partial sums
-template <int N, int M>
+// error integrals with M points per direction; per-cell partial sums; the
+// coefficients xv are in the op's basis BS
+template <int N, int M, int BS>
 __global__ void __launch_bounds__(1024) error_kernel(const GeoArgs g, const double *__restrict__ xv,
                                                      double *__restrict__ part)
 {
   constexpr int N2 = N * N, N3 = N2 * N, M3 = M * M * M;
   constexpr const auto &TN = kTab<N>;
   constexpr const auto &TM = kTab<M>;
+  constexpr const auto &BT = kBasis<N, BS>;
   __shared__ double u[N3];
   __shared__ double red[2][1024];
   const int64_t cell = blockIdx.x;
   const int t = threadIdx.x;
   for (int i = t; i < N3; i += blockDim.x) u[i] = xv[cell * N3 + i];
   __syncthreads();
-  // Gauss-Lobatto Lagrange basis at the M-point Gauss nodes
+  // Gauss-Lobatto Lagrange basis at the M-point Gauss nodes (then the op's basis)
   double lam[N];
   for (int j = 0; j < N; ++j) {
     double p = 1.0;
@@ -412,6 +415,21 @@ __global__ void __launch_bounds__(1024) error_kernel(const GeoArgs g, const doub
         }
         V[d][j] = v;
         D[d][j] = dd;
+      }
+      if constexpr (BS != BASIS_NODAL) {
+        // phi_j = sum_i C[i][j] l_i
+        double v2[N], d2[N];
+        for (int j = 0; j < N; ++j) {
+          v2[j] = d2[j] = 0.0;
+          for (int i = 0; i < N; ++i) {
+            v2[j] += V[d][i] * BT.C[i][j];
+            d2[j] += D[d][i] * BT.C[i][j];
+          }
+        }
+        for (int j = 0; j < N; ++j) {
+          V[d][j] = v2[j];
+          D[d][j] = d2[j];
+        }
       }
     }
     double uh = 0.0, gr[3] = {0.0, 0.0, 0.0};
@@ -554,6 +572,46 @@ dg_status dg_tables(int degree, double *out, size_t len)
   return DG_OK;
 }
 
+dg_status dg_basis_tables(int degree, dg_basis basis, double *out, size_t len)
+{
+  const int n = degree + 1;
+  if (degree < 1 || n > kMaxN) return fail(DG_ERR_ARG, "degree out of range");
+  if (basis != DG_BASIS_NODAL && basis != DG_BASIS_HERMITE) return fail(DG_ERR_ARG, "bad basis");
+  if (basis == DG_BASIS_HERMITE && degree < 3) return fail(DG_ERR_ARG, "the Hermite-like basis needs degree >= 3");
+  if (!out || len < (size_t)(2 * n * n + 4 * n)) return fail(DG_ERR_ARG, "output too short");
+  auto put = [&](const auto &B) {
+    double *o = out;
+    for (int q = 0; q < n; ++q)
+      for (int j = 0; j < n; ++j) *o++ = B.S[q][j];
+    for (int q = 0; q < n; ++q)
+      for (int j = 0; j < n; ++j) *o++ = B.D[q][j];
+    for (int j = 0; j < n; ++j) *o++ = B.V0[j];
+    for (int j = 0; j < n; ++j) *o++ = B.V1[j];
+    for (int j = 0; j < n; ++j) *o++ = B.F0[j];
+    for (int j = 0; j < n; ++j) *o++ = B.F1[j];
+  };
+  auto go = [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    if constexpr (N >= 4)
+      if (basis == DG_BASIS_HERMITE) {
+        put(kBasis<N, BASIS_HERMITE>);
+        return;
+      }
+    put(kBasis<N, BASIS_NODAL>);
+  };
+  switch (n) {
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 3: go(std::integral_constant<int, 3>{}); break;
+    case 4: go(std::integral_constant<int, 4>{}); break;
+    case 5: go(std::integral_constant<int, 5>{}); break;
+    case 6: go(std::integral_constant<int, 6>{}); break;
+    case 7: go(std::integral_constant<int, 7>{}); break;
+    case 8: go(std::integral_constant<int, 8>{}); break;
+    case 9: go(std::integral_constant<int, 9>{}); break;
+  }
+  return DG_OK;
+}
+
 dg_status dg_footprint(const dg_mesh *mesh, int degree, const dg_geometry *geom, const dg_coefficient *coef,
                        unsigned precisions, size_t *bytes)
 {
@@ -598,13 +656,16 @@ dg_status dg_destroy(dg_op *op)
 
 }  // extern "C"
 
-// the SIPG op (vel == nullptr) or the advection op with velocity vel
-static dg_status setup_impl(const dg_mesh *mesh, int degree, const dg_geometry *geom, const dg_coefficient *coef,
-                            const dg_velocity *vel, unsigned precisions, const dg_allocator *alloc, void *stream,
-                            dg_op **out)
+// the SIPG op (vel == nullptr) in the given basis or the advection op with
+// velocity vel (nodal basis)
+static dg_status setup_impl(const dg_mesh *mesh, int degree, int basis, const dg_geometry *geom,
+                            const dg_coefficient *coef, const dg_velocity *vel, unsigned precisions,
+                            const dg_allocator *alloc, void *stream, dg_op **out)
 {
   dg_status st = validate(mesh, degree, geom, coef, precisions);
   if (st != DG_OK) return st;
+  if (basis != DG_BASIS_NODAL && basis != DG_BASIS_HERMITE) return fail(DG_ERR_ARG, "bad basis");
+  if (basis == DG_BASIS_HERMITE && degree < 3) return fail(DG_ERR_ARG, "the Hermite-like basis needs degree >= 3");
   if (!out) return fail(DG_ERR_ARG, "out is null");
   if (alloc && (!alloc->alloc || !alloc->free)) return fail(DG_ERR_ARG, "allocator needs alloc and free");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -615,6 +676,7 @@ static dg_status setup_impl(const dg_mesh *mesh, int degree, const dg_geometry *
   op->geom = *geom;
   op->coef = *coef;
   if (vel) op->vel = *vel;
+  op->basis = basis;
   op->precisions = precisions;
   op->gk = vel ? ADVECTION : geom_kind(geom, coef);
   if (alloc) {
@@ -736,7 +798,14 @@ extern "C" {
 dg_status dg_setup(const dg_mesh *mesh, int degree, const dg_geometry *geom, const dg_coefficient *coef,
                    unsigned precisions, const dg_allocator *alloc, void *stream, dg_op **out)
 {
-  return setup_impl(mesh, degree, geom, coef, nullptr, precisions, alloc, stream, out);
+  return setup_impl(mesh, degree, DG_BASIS_NODAL, geom, coef, nullptr, precisions, alloc, stream, out);
+}
+
+dg_status dg_setup_basis(const dg_mesh *mesh, int degree, dg_basis basis, const dg_geometry *geom,
+                         const dg_coefficient *coef, unsigned precisions, const dg_allocator *alloc, void *stream,
+                         dg_op **out)
+{
+  return setup_impl(mesh, degree, (int)basis, geom, coef, nullptr, precisions, alloc, stream, out);
 }
 
 dg_status dg_setup_advection(const dg_mesh *mesh, int degree, const dg_geometry *geom, const dg_velocity *vel,
@@ -744,7 +813,7 @@ dg_status dg_setup_advection(const dg_mesh *mesh, int degree, const dg_geometry 
 {
   if (!vel || (vel->kind != DG_VEL_CONST && vel->kind != DG_VEL_ROTATION)) return fail(DG_ERR_ARG, "bad velocity");
   const dg_coefficient one{DG_COEF_CONST, 1.0};
-  return setup_impl(mesh, degree, geom, &one, vel, precisions, alloc, stream, out);
+  return setup_impl(mesh, degree, DG_BASIS_NODAL, geom, &one, vel, precisions, alloc, stream, out);
 }
 
 static dg_status check_vec(const dg_op *op, const dg_vec &v, const char *name)
@@ -799,15 +868,24 @@ dg_status dg_rhs(dg_op *op, dg_vec b, void *stream)
   const int block = ((n3 + 63) / 64) * 64;
   double *bp = static_cast<double *>(b.data);
   const int grid = (int)op->ncells;
+  auto go = [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    if constexpr (N >= 4)
+      if (op->basis == BASIS_HERMITE) {
+        hipLaunchKernelGGL((rhs_kernel<N, BASIS_HERMITE>), dim3(grid), dim3(block), 0, s, g, bp);
+        return;
+      }
+    hipLaunchKernelGGL((rhs_kernel<N, BASIS_NODAL>), dim3(grid), dim3(block), 0, s, g, bp);
+  };
   switch (op->n) {
-    case 2: hipLaunchKernelGGL(rhs_kernel<2>, dim3(grid), dim3(block), 0, s, g, bp); break;
-    case 3: hipLaunchKernelGGL(rhs_kernel<3>, dim3(grid), dim3(block), 0, s, g, bp); break;
-    case 4: hipLaunchKernelGGL(rhs_kernel<4>, dim3(grid), dim3(block), 0, s, g, bp); break;
-    case 5: hipLaunchKernelGGL(rhs_kernel<5>, dim3(grid), dim3(block), 0, s, g, bp); break;
-    case 6: hipLaunchKernelGGL(rhs_kernel<6>, dim3(grid), dim3(block), 0, s, g, bp); break;
-    case 7: hipLaunchKernelGGL(rhs_kernel<7>, dim3(grid), dim3(block), 0, s, g, bp); break;
-    case 8: hipLaunchKernelGGL(rhs_kernel<8>, dim3(grid), dim3(block), 0, s, g, bp); break;
-    case 9: hipLaunchKernelGGL(rhs_kernel<9>, dim3(grid), dim3(block), 0, s, g, bp); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 3: go(std::integral_constant<int, 3>{}); break;
+    case 4: go(std::integral_constant<int, 4>{}); break;
+    case 5: go(std::integral_constant<int, 5>{}); break;
+    case 6: go(std::integral_constant<int, 6>{}); break;
+    case 7: go(std::integral_constant<int, 7>{}); break;
+    case 8: go(std::integral_constant<int, 8>{}); break;
+    case 9: go(std::integral_constant<int, 9>{}); break;
   }
   DG_HIP(hipGetLastError());
   return DG_OK;
@@ -827,15 +905,31 @@ dg_status dg_error_manufactured(dg_op *op, dg_vec x, void *stream, double err[2]
   DG_HIP(hipMalloc(&part, sizeof(double) * 2 * op->ncells));
   const double *xp = static_cast<const double *>(x.data);
   const int grid = (int)op->ncells;
+  // M = N + 2 points per direction; the block is the power of two >= M^3
+  // (the kernel's tree reduction needs one), at most 1024 threads
+  auto go = [&](auto nc) {
+    constexpr int N = decltype(nc)::value, M = N + 2;
+    constexpr int block = [] {
+      int b = 64;
+      while (b < M * M * M && b < 1024) b *= 2;
+      return b;
+    }();
+    if constexpr (N >= 4)
+      if (op->basis == BASIS_HERMITE) {
+        hipLaunchKernelGGL((error_kernel<N, M, BASIS_HERMITE>), dim3(grid), dim3(block), 0, s, g, xp, part);
+        return;
+      }
+    hipLaunchKernelGGL((error_kernel<N, M, BASIS_NODAL>), dim3(grid), dim3(block), 0, s, g, xp, part);
+  };
   switch (op->n) {
-    case 2: hipLaunchKernelGGL((error_kernel<2, 4>), dim3(grid), dim3(64), 0, s, g, xp, part); break;
-    case 3: hipLaunchKernelGGL((error_kernel<3, 5>), dim3(grid), dim3(128), 0, s, g, xp, part); break;
-    case 4: hipLaunchKernelGGL((error_kernel<4, 6>), dim3(grid), dim3(256), 0, s, g, xp, part); break;
-    case 5: hipLaunchKernelGGL((error_kernel<5, 7>), dim3(grid), dim3(512), 0, s, g, xp, part); break;
-    case 6: hipLaunchKernelGGL((error_kernel<6, 8>), dim3(grid), dim3(512), 0, s, g, xp, part); break;
-    case 7: hipLaunchKernelGGL((error_kernel<7, 9>), dim3(grid), dim3(1024), 0, s, g, xp, part); break;
-    case 8: hipLaunchKernelGGL((error_kernel<8, 10>), dim3(grid), dim3(1024), 0, s, g, xp, part); break;
-    case 9: hipLaunchKernelGGL((error_kernel<9, 11>), dim3(grid), dim3(1024), 0, s, g, xp, part); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 3: go(std::integral_constant<int, 3>{}); break;
+    case 4: go(std::integral_constant<int, 4>{}); break;
+    case 5: go(std::integral_constant<int, 5>{}); break;
+    case 6: go(std::integral_constant<int, 6>{}); break;
+    case 7: go(std::integral_constant<int, 7>{}); break;
+    case 8: go(std::integral_constant<int, 8>{}); break;
+    case 9: go(std::integral_constant<int, 9>{}); break;
   }
   hipError_t e = hipGetLastError();
   std::vector<double> h(2 * op->ncells);

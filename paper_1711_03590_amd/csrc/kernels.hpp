@@ -3,7 +3,8 @@
 // representation.  One translation unit per N instantiates them.
 //
 // Operator: y = A u (Sec. 2, Eq. (3)) for the SIPG form of Sec. 2, Eq. (2),
-// evaluated cell by cell.  Each workgroup owns B = TPB / N^2 cells and maps
+// evaluated cell by cell, in the nodal Gauss-Lobatto basis or the
+// Hermite-like basis (template parameter BS, see tables.hpp).  Each workgroup owns B = TPB / N^2 cells and maps
 // one thread to one 1D line of each cell (N^2 lines per sweep direction).
 // Per cell, in one pass (Algorithm 1 steps (ii)-(iv) fused, Design Choice 2):
 //   (a) gather the cell's N^3 coefficients into LDS (coalesced block copy);
@@ -12,9 +13,10 @@
 //   (c) per face direction: own-side value and reference normal derivative
 //       at the face points, read off the Gauss-point data with the Gauss
 //       Lagrange end values (the tangential directions already sit at the
-//       face's Gauss points); the neighbour's trace from its Gauss-Lobatto
-//       coefficients (value = end node, normal derivative by D_f of
-//       Eq. (7)), then a 2D basis change S x S to the face Gauss points and
+//       face's Gauss points); the neighbour's trace from its coefficients
+//       on the normal lines (S_f and D_f of Eq. (7): for the nodal basis
+//       the end node and all N nodes, for the Hermite-like basis one and
+//       two coefficients), then a 2D basis change S x S to the face Gauss points and
 //       the collocation derivative along the face for the tangential
 //       gradient; numerical flux of Eq. (2) with the stored
 //       normal-times-inverse-Jacobian j (Design Choice 5); own-side
@@ -33,6 +35,8 @@
 // result is deterministic.  Neighbour blocks are re-read from L2/MALL.
 #pragma once
 
+#include <type_traits>
+
 #include "dg_internal.hpp"
 #include "tables.hpp"
 
@@ -50,8 +54,19 @@ template <int N>
 inline constexpr EvenOdd<N> kEoDcot = make_even_odd<N>(kTab<N>.Dco, true);
 template <int N>
 inline constexpr EvenOdd<N> kEoD = make_even_odd<N>(kTab<N>.D, false);
+template <int N, int BS>
+inline constexpr BasisTables<N> kBasis = make_basis<N>(BS);
+template <int N>
+inline constexpr EvenOdd<N> kEoHS = make_even_odd<N>(kBasis<N, BASIS_HERMITE>.S, false);
+template <int N>
+inline constexpr EvenOdd<N> kEoHSt = make_even_odd<N>(kBasis<N, BASIS_HERMITE>.S, true);
 
-enum : int { M_S = 0, M_ST = 1, M_DCO = 2, M_DCOT = 3, M_D = 4 };
+enum : int { M_S = 0, M_ST = 1, M_DCO = 2, M_DCOT = 3, M_D = 4, M_HS = 5, M_HST = 6 };
+// the basis change of basis BS and its transpose
+template <int BS>
+inline constexpr int kMS = (BS == BASIS_HERMITE) ? M_HS : M_S;
+template <int BS>
+inline constexpr int kMST = (BS == BASIS_HERMITE) ? M_HST : M_ST;
 
 // acc + c x with c a compile-time constant after unrolling: zero and unit
 // coefficients fold away (accumulators start at -0.0, the additive identity)
@@ -73,6 +88,8 @@ __host__ __device__ constexpr EvenOdd<N> eo_tab()
   else if constexpr (M == M_ST) return kEoSt<N>;
   else if constexpr (M == M_DCO) return kEoDco<N>;
   else if constexpr (M == M_DCOT) return kEoDcot<N>;
+  else if constexpr (M == M_HS) return kEoHS<N>;
+  else if constexpr (M == M_HST) return kEoHSt<N>;
   else return kEoD<N>;
 }
 
@@ -83,7 +100,7 @@ template <int N, int M, typename Real>
 __device__ __forceinline__ void eo_apply(const Real (&in)[N], Real (&out)[N])
 {
   constexpr int H = N / 2;
-  constexpr bool sym = (M == M_S || M == M_ST);
+  constexpr bool sym = (M == M_S || M == M_ST || M == M_HS || M == M_HST);
   constexpr EvenOdd<N> C = eo_tab<N, M>();
   Real e[H > 0 ? H : 1], o[H > 0 ? H : 1];
 #pragma unroll
@@ -288,20 +305,30 @@ __device__ __forceinline__ void end_derivatives(const Real (&v)[N], Real &lo, Re
 
 // The two neighbours' normal lines through face point l for direction A;
 // issued ahead of their use so that the loads overlap the preceding phase.
-template <int N, typename Real, int A>
+// Only the coefficients with a non-zero S_f or D_f entry at the shared face
+// are read: all N for the nodal basis, two for the Hermite-like one.
+template <int N, typename Real, int A, int BS>
 __device__ __forceinline__ void load_neighbour_lines(const OpView<Real> &op, const Real *__restrict__ src,
                                                      int cell, int l, const int (&ci)[3], Real (&nb)[2][N])
 {
   // branch-free: a missing neighbour reads the cell itself (the values are
   // then ignored), so the loads can stay in flight across later phases
   constexpr int N3 = N * N * N;
+  constexpr BasisTables<N> BT = kBasis<N, BS>;
   const int64_t cstride = (A == 0) ? 1 : (A == 1 ? (int64_t)op.ncell[0] : (int64_t)op.ncell[0] * op.ncell[1]);
+  const int b = line_base<N, A>(l);
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const int cn = ci[A] + (s ? 1 : -1);
     const bool inside = cn >= 0 && cn < op.ncell[A];
     const int64_t nbc = inside ? (int64_t)cell + (s ? cstride : -cstride) : (int64_t)cell;
-    load_line<N, A>(src + nbc * N3, l, nb[s]);
+    const Real *line = src + nbc * N3 + b;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      // the neighbour below meets the face with its xi_A = 1 side, the one above with xi_A = 0
+      const bool need = s ? (BT.V0[m] != 0.0 || BT.F0[m] != 0.0) : (BT.V1[m] != 0.0 || BT.F1[m] != 0.0);
+      nb[s][m] = need ? line[m * kStride<N, A>] : Real(0);
+    }
   }
 }
 
@@ -327,7 +354,7 @@ __device__ __forceinline__ void for_jobs(int l, bool act, F &&f)
 //   [[u]] = u- - u+, {{grad u}} = (grad u- + grad u+)/2; the average's
 //   tangential part is the tangential derivative of V = u- + u+ on the face
 //   (V = 2 u- on a Dirichlet face, where u+ = -u- but grad u+ = grad u-).
-template <int N, typename Real, int GK, int A, typename Next>
+template <int N, typename Real, int GK, int A, int BS, typename Next>
 __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Real *Q, Real *R, Real *W, int l,
                                                const int (&ci)[3], bool act, bool valid, const Real (&nb)[2][N],
                                                Real (&fz)[4], Next &&next)
@@ -335,7 +362,8 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
   constexpr int N2 = N * N;
   constexpr int t1 = (A == 0) ? 1 : 0, t2 = (A == 2) ? 1 : 2;
   constexpr Tables<N> T = kTab<N>;
-  Real *X = W;            // [s][value, normal derivative] of the neighbour at Gauss-Lobatto face nodes p1 + N p2
+  constexpr BasisTables<N> BT = kBasis<N, BS>;
+  Real *X = W;            // [s][value, normal derivative] of the neighbour as face coefficients p1 + N p2
   Real *Y = W + 4 * N2;   // [s][..] after the basis change along t1: q1 + N p2
   Real *U = W;            // [s][u+, d_A u+] at the face Gauss points q1 + N q2
   Real *V = W + 8 * N2;   // [s] u- + u+
@@ -353,8 +381,8 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
   face_geometry<N, Real, GK, A>(op, ci, 1, l, jg[1], cds[1]);
   // S1: own value and reference normal derivative at this face point (the
   // Gauss-point data is tangentially at the face's Gauss points already);
-  // the neighbour's value and normal derivative at the Gauss-Lobatto nodes of
-  // the shared face: end node (nodal basis) and D_f of Eq. (7)
+  // the neighbour's value and normal derivative on the shared face in the
+  // tangential basis: S_f and D_f of Eq. (7) applied to its normal line
   Real um[2], dm[2];
   if (act) {
     Real v[N];
@@ -362,15 +390,17 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
     end_values<N>(v, um[0], um[1]);
     end_derivatives<N>(v, dm[0], dm[1]);
     // neighbour below: the shared face is its xi_A = 1 side; above: xi_A = 0
-    Real der0 = Real(-0.0), der1 = Real(-0.0);
+    Real val0 = Real(-0.0), der0 = Real(-0.0), val1 = Real(-0.0), der1 = Real(-0.0);
 #pragma unroll
     for (int m = 0; m < N; ++m) {
-      der0 = madd(T.F1[m], nb[0][m], der0);
-      der1 = madd(T.F0[m], nb[1][m], der1);
+      val0 = madd(BT.V1[m], nb[0][m], val0);
+      der0 = madd(BT.F1[m], nb[0][m], der0);
+      val1 = madd(BT.V0[m], nb[1][m], val1);
+      der1 = madd(BT.F0[m], nb[1][m], der1);
     }
-    X[0 * N2 + l] = nb[0][N - 1];
+    X[0 * N2 + l] = val0;
     X[1 * N2 + l] = der0;
-    X[2 * N2 + l] = nb[1][0];
+    X[2 * N2 + l] = val1;
     X[3 * N2 + l] = der1;
   }
   __syncthreads();
@@ -384,7 +414,7 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
     Real v[N], r[N];
 #pragma unroll
     for (int m = 0; m < N; ++m) v[m] = X[a * N2 + m + N * p2];
-    eo_apply<N, M_S>(v, r);
+    eo_apply<N, kMS<BS>>(v, r);
 #pragma unroll
     for (int m = 0; m < N; ++m) Y[a * N2 + m + N * p2] = r[m];
   });
@@ -395,7 +425,7 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
     Real v[N], r[N];
 #pragma unroll
     for (int m = 0; m < N; ++m) v[m] = Y[a * N2 + q1 + N * m];
-    eo_apply<N, M_S>(v, r);
+    eo_apply<N, kMS<BS>>(v, r);
 #pragma unroll
     for (int m = 0; m < N; ++m) U[a * N2 + q1 + N * m] = r[m];
   });
@@ -523,7 +553,7 @@ __device__ __forceinline__ Real wg_sum(Real v, Real *sh)
 
 // The fused pass over the cells of one batch (cells blk*B .. blk*B+B-1) by
 // a workgroup of TPB threads; smem holds B * (2 N^3 + WSZ) values.
-template <int N, typename Real, int GK, int TPB, bool DOT = false>
+template <int N, typename Real, int GK, int TPB, bool DOT = false, int BS = BASIS_NODAL>
 __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *__restrict__ src,
                                             Real *__restrict__ dst, int blk, Real *smem,
                                             const DotOut<Real> &dot = DotOut<Real>{})
@@ -562,7 +592,7 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
   for (int j = 0; j < GI; ++j) gv[j] = src[g0 + min(t + j * TPB, nhere * N3 - 1)];
   __builtin_amdgcn_sched_barrier(0);  // keep the gather ahead of the neighbour loads
   Real nb[2][N];
-  load_neighbour_lines<N, Real, 0>(op, src, cell, l, ci, nb);
+  load_neighbour_lines<N, Real, 0, BS>(op, src, cell, l, ci, nb);
   // (slots past B N^3 fall into R, which the first face direction overwrites)
   static_assert(GI * TPB <= 2 * B * N3, "gather overrun");
 #pragma unroll
@@ -573,11 +603,11 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
   __syncthreads();
 
   // (b) basis change to the Gauss points (Eq. (6), right factor)
-  if (act) sweep<N, 0, M_S>(Q, Q, l);
+  if (act) sweep<N, 0, kMS<BS>>(Q, Q, l);
   __syncthreads();
-  if (act) sweep<N, 1, M_S>(Q, Q, l);
+  if (act) sweep<N, 1, kMS<BS>>(Q, Q, l);
   __syncthreads();
-  if (act) sweep<N, 2, M_S>(Q, Q, l);
+  if (act) sweep<N, 2, kMS<BS>>(Q, Q, l);
   __syncthreads();
 
   // (c) face terms, direction by direction, into R; the stored cell geometry
@@ -594,12 +624,12 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
     }
   };
   Real fz[4] = {Real(0), Real(0), Real(0), Real(0)};
-  face_direction<N, Real, GK, 0>(op, Q, R, W, l, ci, act, valid, nb, fz,
-                                 [&] { load_neighbour_lines<N, Real, 1>(op, src, cell, l, ci, nb); });
-  face_direction<N, Real, GK, 1>(op, Q, R, W, l, ci, act, valid, nb, fz,
-                                 [&] { load_neighbour_lines<N, Real, 2>(op, src, cell, l, ci, nb); });
+  face_direction<N, Real, GK, 0, BS>(op, Q, R, W, l, ci, act, valid, nb, fz,
+                                     [&] { load_neighbour_lines<N, Real, 1, BS>(op, src, cell, l, ci, nb); });
+  face_direction<N, Real, GK, 1, BS>(op, Q, R, W, l, ci, act, valid, nb, fz,
+                                     [&] { load_neighbour_lines<N, Real, 2, BS>(op, src, cell, l, ci, nb); });
   constexpr int PRE = (DG_GEO_PRE < NB) ? DG_GEO_PRE : NB;
-  face_direction<N, Real, GK, 2>(op, Q, R, W, l, ci, act, valid, nb, fz, [&] {
+  face_direction<N, Real, GK, 2, BS>(op, Q, R, W, l, ci, act, valid, nb, fz, [&] {
 #pragma unroll
     for (int k = 0; k < PRE; ++k) load_geometry(k, gbuf[k]);
   });
@@ -703,11 +733,11 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
   __syncthreads();
 
   // (e) back to the Gauss-Lobatto basis (transposed basis change) and write
-  if (act) sweep<N, 0, M_ST>(R, R, l);
+  if (act) sweep<N, 0, kMST<BS>>(R, R, l);
   __syncthreads();
-  if (act) sweep<N, 1, M_ST>(R, R, l);
+  if (act) sweep<N, 1, kMST<BS>>(R, R, l);
   __syncthreads();
-  if (act) sweep<N, 2, M_ST>(R, R, l);
+  if (act) sweep<N, 2, kMST<BS>>(R, R, l);
   __syncthreads();
   const Real *Rall = smem + B * N3;
   for (int i = t; i < nhere * N3; i += TPB) dst[g0 + i] = Rall[i];
@@ -726,14 +756,14 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
   }
 }
 
-template <int N, typename Real, int GK, bool DOT = false>
+template <int N, typename Real, int GK, bool DOT = false, int BS = BASIS_NODAL>
 __global__ void __launch_bounds__(Blocking<N>::TPB, (Occupancy<N, Real>::value))
 sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__restrict__ dst,
                   const DotOut<Real> dot = DotOut<Real>{})
 {
   using BK = Blocking<N>;
   __shared__ Real smem[BK::SMEM];
-  apply_batch<N, Real, GK, BK::TPB, DOT>(op, src, dst, xcd_remap(blockIdx.x, gridDim.x), smem, dot);
+  apply_batch<N, Real, GK, BK::TPB, DOT, BS>(op, src, dst, xcd_remap(blockIdx.x, gridDim.x), smem, dot);
 }
 
 // ---------------------------------------------------------------------------
@@ -746,18 +776,21 @@ sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__r
 //          components the sum over the n^3 points factorises into three 1D
 //          contractions with the tables F_d[q][j] = E_b,d[q][j] E_c,d[q][j]:
 //          O(n^4) per pair instead of O(n^6) for the whole cell.
-//   faces: phi_i vanishes on a face unless i sits on it (nodal basis); there
+//   faces: phi_i vanishes on a face unless its 1D factor normal to the face
+//          is the one with value 1 there (the end node of the nodal basis,
+//          phi_0 or phi_{N-1} of the Hermite-like one); there
 //          sum_q c ds (tau phi_i^2 - phi_i dn phi_i) (interior neighbour has u = 0),
 //          twice that on Dirichlet faces (mirror), nothing on Neumann faces.
 // Accumulated in double from the FP64 geometry.
 // ---------------------------------------------------------------------------
-template <int N, int GK>
+template <int N, int GK, int BS = BASIS_NODAL>
 __global__ void __launch_bounds__(1024)
 sipg_diag_kernel(const OpView<double> op, double *__restrict__ d64, float *__restrict__ d32)
 {
   constexpr int N2 = N * N, N3 = N2 * N;
   constexpr Tables<N> T = kTab<N>;
-  __shared__ double Sl[N2], Dl[N2];      // S[q][j], D[q][j] (Lobatto basis j at Gauss point q)
+  constexpr BasisTables<N> BT = kBasis<N, BS>;
+  __shared__ double Sl[N2], Dl[N2];      // S[q][j], D[q][j] (basis function j at Gauss point q)
   __shared__ double Fe[2 * N];           // D_f end rows: F0[j], F1[j]
   __shared__ double M[6 * N3];           // M00 M01 M02 M11 M12 M22 per point
   __shared__ double T1[N3], T2[N3];
@@ -769,11 +802,11 @@ sipg_diag_kernel(const OpView<double> op, double *__restrict__ d64, float *__res
     for (int q = 0; q < N; ++q) {
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        Sl[q * N + j] = T.S[q][j];
-        Dl[q * N + j] = T.D[q][j];
+        Sl[q * N + j] = BT.S[q][j];
+        Dl[q * N + j] = BT.D[q][j];
       }
-      Fe[q] = T.F0[q];
-      Fe[N + q] = T.F1[q];
+      Fe[q] = BT.F0[q];
+      Fe[N + q] = BT.F1[q];
     }
   }
   // effective coefficient at quadrature point q = i
@@ -900,33 +933,49 @@ sipg_diag_kernel(const OpView<double> op, double *__restrict__ d64, float *__res
 
 namespace dgk {
 
+// f(gk, bs) with the op's SIPG geometry kind and basis as compile-time
+// constants (the Hermite-like basis exists from N = 4 on)
+template <int N, typename F>
+__host__ void sipg_variant(const dg_op *op, F &&f)
+{
+  auto with_gk = [&](auto bs) {
+    switch (op->gk) {
+      case CURVED: f(std::integral_constant<int, CURVED>{}, bs); break;
+      case CURVED_MERGED: f(std::integral_constant<int, CURVED_MERGED>{}, bs); break;
+      case AFFINE_VAR: f(std::integral_constant<int, AFFINE_VAR>{}, bs); break;
+      default: f(std::integral_constant<int, AFFINE_CONST>{}, bs); break;
+    }
+  };
+  if constexpr (N >= 4) {
+    if (op->basis == BASIS_HERMITE) {
+      with_gk(std::integral_constant<int, BASIS_HERMITE>{});
+      return;
+    }
+  }
+  with_gk(std::integral_constant<int, BASIS_NODAL>{});
+}
+
 template <int N>
 hipError_t launch_apply(const dg_op *op, const void *src, void *dst, bool f32, hipStream_t s)
 {
   using BK = Blocking<N>;
   const int grid = (int)((op->ncells + BK::B - 1) / BK::B);
   if (grid == 0) return hipSuccess;
-  if (f32) {
-    const float *x = static_cast<const float *>(src);
-    float *y = static_cast<float *>(dst);
-    switch (op->gk) {
-      case CURVED: hipLaunchKernelGGL((sipg_apply_kernel<N, float, CURVED>), dim3(grid), dim3(BK::TPB), 0, s, op->v32, x, y); break;
-      case CURVED_MERGED: hipLaunchKernelGGL((sipg_apply_kernel<N, float, CURVED_MERGED>), dim3(grid), dim3(BK::TPB), 0, s, op->v32, x, y); break;
-      case ADVECTION: hipLaunchKernelGGL((adv_apply_kernel<N, float>), dim3(grid), dim3(BK::TPB), 0, s, op->v32, x, y); break;
-      case AFFINE_VAR: hipLaunchKernelGGL((sipg_apply_kernel<N, float, AFFINE_VAR>), dim3(grid), dim3(BK::TPB), 0, s, op->v32, x, y); break;
-      default: hipLaunchKernelGGL((sipg_apply_kernel<N, float, AFFINE_CONST>), dim3(grid), dim3(BK::TPB), 0, s, op->v32, x, y); break;
+  auto go = [&](auto zero, const auto &view) {
+    using Real = decltype(zero);
+    const Real *x = static_cast<const Real *>(src);
+    Real *y = static_cast<Real *>(dst);
+    if (op->gk == ADVECTION) {
+      hipLaunchKernelGGL((adv_apply_kernel<N, Real>), dim3(grid), dim3(BK::TPB), 0, s, view, x, y);
+      return;
     }
-  } else {
-    const double *x = static_cast<const double *>(src);
-    double *y = static_cast<double *>(dst);
-    switch (op->gk) {
-      case CURVED: hipLaunchKernelGGL((sipg_apply_kernel<N, double, CURVED>), dim3(grid), dim3(BK::TPB), 0, s, op->v64, x, y); break;
-      case CURVED_MERGED: hipLaunchKernelGGL((sipg_apply_kernel<N, double, CURVED_MERGED>), dim3(grid), dim3(BK::TPB), 0, s, op->v64, x, y); break;
-      case ADVECTION: hipLaunchKernelGGL((adv_apply_kernel<N, double>), dim3(grid), dim3(BK::TPB), 0, s, op->v64, x, y); break;
-      case AFFINE_VAR: hipLaunchKernelGGL((sipg_apply_kernel<N, double, AFFINE_VAR>), dim3(grid), dim3(BK::TPB), 0, s, op->v64, x, y); break;
-      default: hipLaunchKernelGGL((sipg_apply_kernel<N, double, AFFINE_CONST>), dim3(grid), dim3(BK::TPB), 0, s, op->v64, x, y); break;
-    }
-  }
+    sipg_variant<N>(op, [&](auto gk, auto bs) {
+      hipLaunchKernelGGL((sipg_apply_kernel<N, Real, decltype(gk)::value, false, decltype(bs)::value>), dim3(grid),
+                         dim3(BK::TPB), 0, s, view, x, y, DotOut<Real>{});
+    });
+  };
+  if (f32) go(0.0f, op->v32);
+  else go(0.0, op->v64);
   return hipGetLastError();
 }
 
@@ -943,12 +992,10 @@ hipError_t launch_apply_dot(const dg_op *op, const void *src, void *dst, bool f3
     const Real *x = static_cast<const Real *>(src);
     Real *y = static_cast<Real *>(dst);
     DotOut<Real> d{static_cast<Real *>(part)};
-    switch (op->gk) {
-      case CURVED: hipLaunchKernelGGL((sipg_apply_kernel<N, Real, CURVED, true>), dim3(grid), dim3(BK::TPB), 0, s, view, x, y, d); break;
-      case CURVED_MERGED: hipLaunchKernelGGL((sipg_apply_kernel<N, Real, CURVED_MERGED, true>), dim3(grid), dim3(BK::TPB), 0, s, view, x, y, d); break;
-      case AFFINE_VAR: hipLaunchKernelGGL((sipg_apply_kernel<N, Real, AFFINE_VAR, true>), dim3(grid), dim3(BK::TPB), 0, s, view, x, y, d); break;
-      default: hipLaunchKernelGGL((sipg_apply_kernel<N, Real, AFFINE_CONST, true>), dim3(grid), dim3(BK::TPB), 0, s, view, x, y, d); break;
-    }
+    sipg_variant<N>(op, [&](auto gk, auto bs) {
+      hipLaunchKernelGGL((sipg_apply_kernel<N, Real, decltype(gk)::value, true, decltype(bs)::value>), dim3(grid),
+                         dim3(BK::TPB), 0, s, view, x, y, d);
+    });
   };
   if (f32) go(0.0f, op->v32);
   else go(0.0, op->v64);
@@ -970,12 +1017,10 @@ hipError_t launch_diag(const dg_op *op, void *diag64, void *diag32, hipStream_t 
   if (grid == 0) return hipSuccess;
   double *d64 = static_cast<double *>(diag64);
   float *d32 = static_cast<float *>(diag32);
-  switch (op->gk) {
-    case CURVED: hipLaunchKernelGGL((sipg_diag_kernel<N, CURVED>), dim3(grid), dim3(block), 0, s, op->v64, d64, d32); break;
-    case CURVED_MERGED: hipLaunchKernelGGL((sipg_diag_kernel<N, CURVED_MERGED>), dim3(grid), dim3(block), 0, s, op->v64, d64, d32); break;
-    case AFFINE_VAR: hipLaunchKernelGGL((sipg_diag_kernel<N, AFFINE_VAR>), dim3(grid), dim3(block), 0, s, op->v64, d64, d32); break;
-    default: hipLaunchKernelGGL((sipg_diag_kernel<N, AFFINE_CONST>), dim3(grid), dim3(block), 0, s, op->v64, d64, d32); break;
-  }
+  sipg_variant<N>(op, [&](auto gk, auto bs) {
+    hipLaunchKernelGGL((sipg_diag_kernel<N, decltype(gk)::value, decltype(bs)::value>), dim3(grid), dim3(block), 0, s,
+                       op->v64, d64, d32);
+  });
   return hipGetLastError();
 }
 

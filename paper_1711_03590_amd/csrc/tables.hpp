@@ -175,6 +175,108 @@ constexpr Tables<N> make_tables()
   return T;
 }
 
+// The two bases of the SIPG operator, as 1D tables:
+//   S[q][j] = phi_j(gx[q]), D[q][j] = phi_j'(gx[q]),
+//   V0, V1  phi_j(0), phi_j(1)      S_f of Eq. (7) at the two ends
+//   F0, F1  phi_j'(0), phi_j'(1)    D_f of Eq. (7) at the two ends
+//   C       phi_j = sum_i C[i][j] l_i with l_i the Lagrange polynomials on the
+//           Gauss-Lobatto points (the identity for the nodal basis)
+// BASIS_NODAL: Lagrange on the Gauss-Lobatto points (face values from one
+// node per normal line, face derivatives from all N).
+// BASIS_HERMITE (N >= 4): the Hermite-like basis dual to the functionals
+//   u(0), s u'(0), u(lx[2]), ..., u(lx[N-3]), -s u'(1), u(1),   s = lx[1],
+// so that a face value needs one coefficient per normal line and a face
+// derivative one more (phi_0, phi_1 at 0; phi_{N-1}, phi_{N-2} at 1), which
+// is what a Hermite-type basis buys for the face kernels (Sec. 3, Eq. (7)).
+enum : int { BASIS_NODAL = 0, BASIS_HERMITE = 1 };
+
+template <int N>
+struct BasisTables {
+  double S[N][N], D[N][N];
+  double V0[N], V1[N], F0[N], F1[N];
+  double C[N][N];
+};
+
+template <int N>
+constexpr BasisTables<N> make_basis(int basis)
+{
+  const Tables<N> T = make_tables<N>();
+  BasisTables<N> B{};
+  if (basis == BASIS_NODAL || N < 4) {
+    for (int q = 0; q < N; ++q)
+      for (int j = 0; j < N; ++j) {
+        B.S[q][j] = T.S[q][j];
+        B.D[q][j] = T.D[q][j];
+        B.C[q][j] = (q == j) ? 1.0 : 0.0;
+      }
+    for (int j = 0; j < N; ++j) {
+      B.V0[j] = (j == 0) ? 1.0 : 0.0;
+      B.V1[j] = (j == N - 1) ? 1.0 : 0.0;
+      B.F0[j] = T.F0[j];
+      B.F1[j] = T.F1[j];
+    }
+    return B;
+  }
+  // functional m applied to Lagrange polynomial i: G[m][i]; C = G^{-1}
+  const double s = T.lx[1];
+  double G[N][N]{}, I[N][N]{};
+  for (int m = 0; m < N; ++m) {
+    for (int i = 0; i < N; ++i) {
+      if (m == 1) G[m][i] = s * T.F0[i];
+      else if (m == N - 2) G[m][i] = -s * T.F1[i];
+      else G[m][i] = (m == i) ? 1.0 : 0.0;
+      I[m][i] = (m == i) ? 1.0 : 0.0;
+    }
+  }
+  // Gauss-Jordan elimination with partial pivoting
+  for (int c = 0; c < N; ++c) {
+    int p = c;
+    for (int r = c + 1; r < N; ++r)
+      if (c_abs(G[r][c]) > c_abs(G[p][c])) p = r;
+    for (int k = 0; k < N; ++k) {
+      const double a = G[c][k], b = I[c][k];
+      G[c][k] = G[p][k];
+      I[c][k] = I[p][k];
+      G[p][k] = a;
+      I[p][k] = b;
+    }
+    const double piv = G[c][c];
+    for (int k = 0; k < N; ++k) {
+      G[c][k] /= piv;
+      I[c][k] /= piv;
+    }
+    for (int r = 0; r < N; ++r) {
+      if (r == c) continue;
+      const double f = G[r][c];
+      for (int k = 0; k < N; ++k) {
+        G[r][k] -= f * G[c][k];
+        I[r][k] -= f * I[c][k];
+      }
+    }
+  }
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) B.C[i][j] = I[i][j];
+  for (int q = 0; q < N; ++q)
+    for (int j = 0; j < N; ++j) {
+      double sv = 0.0, dv = 0.0;
+      for (int i = 0; i < N; ++i) {
+        sv += T.S[q][i] * B.C[i][j];
+        dv += T.D[q][i] * B.C[i][j];
+      }
+      B.S[q][j] = sv;
+      B.D[q][j] = dv;
+    }
+  // the end data are the defining functionals themselves, kept exact so
+  // that the kernels skip the zero entries
+  for (int j = 0; j < N; ++j) {
+    B.V0[j] = (j == 0) ? 1.0 : 0.0;
+    B.V1[j] = (j == N - 1) ? 1.0 : 0.0;
+    B.F0[j] = (j == 1) ? 1.0 / s : 0.0;
+    B.F1[j] = (j == N - 2) ? -1.0 / s : 0.0;
+  }
+  return B;
+}
+
 // Even-odd split of a centro-(skew-)symmetric N x N matrix M with
 // M[N-1-i][N-1-j] = sym * M[i][j] (Sec. 3.3, Eq. (8)):
 //   E[i][j] = (M[i][j] + M[i][N-1-j]) / 2,  O[i][j] = (M[i][j] - M[i][N-1-j]) / 2

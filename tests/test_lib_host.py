@@ -139,3 +139,40 @@ def test_build_entry_compiles_the_oracle():
     import oracle
     path = oracle.build(force=True)
     assert os.path.exists(path) and path.endswith("liboracle.so")
+
+
+@pytest.mark.parametrize("k", range(3, 9))
+def test_basis_tables_match_the_oracle(dg, orc, k):
+    """The library's compiled-in Hermite-like and nodal tables against the
+    oracle's own construction of the same bases."""
+    n = k + 1
+    gx, _ = orc.gauss(n)
+    for basis, obasis in (("hermite", "hermite"), ("nodal", "gll")):
+        t = dg.basis_tables(k, basis)
+        S = np.array([[orc.basis1d(n, obasis, j, x)[0] for j in range(n)] for x in gx])
+        D = np.array([[orc.basis1d(n, obasis, j, x)[1] for j in range(n)] for x in gx])
+        assert np.abs(t["S"] - S).max() <= 1e-13
+        assert np.abs(t["D"] - D).max() <= 1e-12 * np.abs(D).max()
+        for key, x, der in (("V0", 0.0, 0), ("V1", 1.0, 0), ("F0", 0.0, 1), ("F1", 1.0, 1)):
+            ref = np.array([orc.basis1d(n, obasis, j, x)[der] for j in range(n)])
+            assert np.abs(t[key] - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+    h = dg.basis_tables(k, "hermite")
+    # face locality: one coefficient for the value and one for the slope at each end
+    assert np.count_nonzero(h["V0"]) == 1 and np.count_nonzero(h["F0"]) == 1
+    assert np.count_nonzero(h["V1"]) == 1 and np.count_nonzero(h["F1"]) == 1
+
+
+def test_bad_basis_rejected(dg):
+    import ctypes
+    m = dg.make_mesh(4, (dg.DIRICHLET,) * 6)
+    g = dg.Geometry(dg.MAP_SINE, 0.05, 0)
+    c = dg.Coefficient(0, 1.0)
+    h = ctypes.c_void_p()
+    for degree, basis in ((3, 7), (2, dg.BASIS_HERMITE)):
+        st = dg.lib().dg_setup_basis(ctypes.byref(m), degree, basis, ctypes.byref(g), ctypes.byref(c), dg.PREC_F64,
+                                     None, None, ctypes.byref(h))
+        assert st == dg.DG_ERR_ARG
+    with pytest.raises(dg.DGError):
+        dg.basis_tables(2, "hermite")
+    with pytest.raises(ValueError):
+        dg.basis_tables(3, "legendre")
