@@ -75,10 +75,14 @@ typedef enum { DG_MAP_AFFINE = 0, DG_MAP_SINE = 1 } dg_map;
 /* What a curved map stores per cell quadrature point (Sec. 5):
  * DG_STORE_JACOBIAN  the inverse Jacobian and c det J w, 10 values (G3);
  * DG_STORE_MERGED    the symmetric effective coefficient
- *                    c det J w J^{-1} J^{-T} of the Laplacian, 6 values (G4).
- * Both give the same operator up to rounding; faces store j = J^{-1} n and
+ *                    c det J w J^{-1} J^{-T} of the Laplacian, 6 values (G4);
+ * DG_STORE_MIXED     G3 for the FP64 data and G4 for the FP32 data: FP64
+ *                    applies (the residuals of mixed-precision refinement)
+ *                    see the stored Jacobians, FP32 applies (the inner
+ *                    solver) the cheaper merged coefficient.
+ * All give the same operator up to rounding; faces store j = J^{-1} n and
  * c ds either way.  Ignored for DG_MAP_AFFINE. */
-typedef enum { DG_STORE_JACOBIAN = 0, DG_STORE_MERGED = 1 } dg_storage;
+typedef enum { DG_STORE_JACOBIAN = 0, DG_STORE_MERGED = 1, DG_STORE_MIXED = 2 } dg_storage;
 typedef struct {
   dg_map map;
   double amplitude;

@@ -18,7 +18,18 @@ DG_OK, DG_ERR_ARG, DG_ERR_OOM, DG_ERR_HIP, DG_ERR_UNSUPPORTED, DG_ERR_NOT_CONVER
 F64, F32 = 0, 1
 DIRICHLET, NEUMANN = 0, 1
 MAP_AFFINE, MAP_SINE = 0, 1
-STORE_JACOBIAN, STORE_MERGED = 0, 1
+STORE_JACOBIAN, STORE_MERGED, STORE_MIXED = 0, 1, 2
+
+
+def _storage(merged, storage):
+    """storage "jacobian" (G3), "merged" (G4) or "mixed" (G3 in FP64, G4 in
+    FP32); merged=True is short for "merged"."""
+    if storage is None:
+        storage = "merged" if merged else "jacobian"
+    table = {"jacobian": STORE_JACOBIAN, "merged": STORE_MERGED, "mixed": STORE_MIXED}
+    if storage not in table:
+        raise ValueError("storage must be 'jacobian', 'merged' or 'mixed'")
+    return table[storage]
 COEF_CONST, COEF_SINCOS = 0, 1
 PREC_F64, PREC_F32 = 1, 2
 BASIS_NODAL, BASIS_HERMITE = 0, 1
@@ -194,9 +205,9 @@ def make_mesh(ncell, bc=(DIRICHLET,) * 6, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)
 
 
 def footprint(ncell, degree, *, curved=False, amplitude=0.05, variable_coef=False, coef_value=1.0,
-              precisions=PREC_F64 | PREC_F32, bc=(DIRICHLET,) * 6, merged=False):
+              precisions=PREC_F64 | PREC_F32, bc=(DIRICHLET,) * 6, merged=False, storage=None):
     m = make_mesh(ncell, bc)
-    g = Geometry(MAP_SINE if curved else MAP_AFFINE, amplitude, STORE_MERGED if merged else STORE_JACOBIAN)
+    g = Geometry(MAP_SINE if curved else MAP_AFFINE, amplitude, _storage(merged, storage))
     c = Coefficient(COEF_SINCOS if variable_coef else COEF_CONST, coef_value)
     out = ctypes.c_size_t()
     check(lib().dg_footprint(ctypes.byref(m), degree, ctypes.byref(g), ctypes.byref(c), precisions,
@@ -268,19 +279,22 @@ class Operator:
 
     def __init__(self, ncell, degree, *, curved=False, amplitude=0.05, variable_coef=False, coef_value=1.0,
                  bc=(DIRICHLET,) * 6, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
-                 precisions=PREC_F64 | PREC_F32, torch_alloc=True, stream=None, merged=False, basis="nodal"):
+                 precisions=PREC_F64 | PREC_F32, torch_alloc=True, stream=None, merged=False, basis="nodal",
+                 storage=None):
         self._h = None
         self.degree = degree
         self.mesh = make_mesh(ncell, bc, lo, hi)
         self.ncell = tuple(self.mesh.ncell)
         self.curved = curved
-        self.merged = merged and curved
+        st = _storage(merged, storage)
+        self.merged = curved and st == STORE_MERGED
+        self.storage = st
         self.variable_coef = variable_coef
         self.precisions = precisions
         self.basis = basis
         b = _basis(basis)
         self._alloc = TorchAllocator() if torch_alloc else None
-        g = Geometry(MAP_SINE if curved else MAP_AFFINE, amplitude, STORE_MERGED if merged else STORE_JACOBIAN)
+        g = Geometry(MAP_SINE if curved else MAP_AFFINE, amplitude, st)
         c = Coefficient(COEF_SINCOS if variable_coef else COEF_CONST, coef_value)
         h = ctypes.c_void_p()
         alloc = ctypes.byref(self._alloc.struct) if self._alloc else None

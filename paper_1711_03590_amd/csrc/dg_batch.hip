@@ -243,7 +243,7 @@ dg_status rebuild(dg_batch *b, hipStream_t s)
     const int cells_per_item = kBatchTpb / (n * n);
     d.v = r.op->v32;
     d.n = n;
-    d.gk = r.op->gk;
+    d.gk = r.op->gk32;
     d.ndofs = r.op->ndofs;
     d.item0 = item;
     d.nitems = (int)((r.op->ncells + cells_per_item - 1) / cells_per_item);

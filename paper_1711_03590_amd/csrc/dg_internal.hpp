@@ -72,7 +72,8 @@ struct dg_op {
   dg_velocity vel{};         // advection ops only
   int basis = 0;             // SIPG ops: DG_BASIS_NODAL or DG_BASIS_HERMITE
   unsigned precisions = 0;
-  int gk = 0;
+  int gk = 0;                // geometry kind of the FP64 data (and of the op)
+  int gk32 = 0;              // geometry kind of the FP32 data (differs for DG_STORE_MIXED)
   int64_t ncells = 0, ndofs = 0, nfaces[3] = {0, 0, 0};
   double h[3] = {0, 0, 0};
   int device = 0;

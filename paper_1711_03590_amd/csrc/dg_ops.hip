@@ -491,24 +491,31 @@ static GeoArgs geo_args(const dg_op *op)
 static int64_t geom_cell_values(int gk) { return cell_values(gk); }
 static int64_t geom_face_values(int gk) { return face_values(gk); }
 
-static int geom_kind(const dg_geometry *geom, const dg_coefficient *coef)
+// geometry kind of the FP64 (f32 = false) or FP32 data
+static int geom_kind(const dg_geometry *geom, const dg_coefficient *coef, bool f32 = false)
 {
-  if (geom->map == DG_MAP_SINE) return geom->storage == DG_STORE_MERGED ? CURVED_MERGED : CURVED;
+  if (geom->map == DG_MAP_SINE) {
+    if (geom->storage == DG_STORE_MERGED || (f32 && geom->storage == DG_STORE_MIXED)) return CURVED_MERGED;
+    return CURVED;
+  }
   return coef->kind == DG_COEF_SINCOS ? AFFINE_VAR : AFFINE_CONST;
 }
 
-static size_t footprint_bytes(const int64_t nc[3], int n, int gk, unsigned prec)
+static size_t footprint_bytes(const int64_t nc[3], int n, int gk64, int gk32, unsigned prec)
 {
   const int64_t ncells = nc[0] * nc[1] * nc[2];
   const int64_t n2 = n * n, n3 = n2 * n;
-  int64_t vals = geom_cell_values(gk) * ncells * n3;
-  for (int a = 0; a < 3; ++a) {
-    const int64_t nf = ncells / nc[a] * (nc[a] + 1);
-    vals += geom_face_values(gk) * nf * n2;
-  }
+  auto values = [&](int gk) {
+    int64_t vals = geom_cell_values(gk) * ncells * n3;
+    for (int a = 0; a < 3; ++a) {
+      const int64_t nf = ncells / nc[a] * (nc[a] + 1);
+      vals += geom_face_values(gk) * nf * n2;
+    }
+    return vals;
+  };
   size_t bytes = 0;
-  if (prec & DG_PREC_F64) bytes += vals * 8 + ncells * n3 * 8;
-  if (prec & DG_PREC_F32) bytes += vals * 4 + ncells * n3 * 4;
+  if (prec & DG_PREC_F64) bytes += values(gk64) * 8 + ncells * n3 * 8;
+  if (prec & DG_PREC_F32) bytes += values(gk32) * 4 + ncells * n3 * 4;
   return bytes;
 }
 
@@ -527,7 +534,7 @@ static dg_status validate(const dg_mesh *mesh, int degree, const dg_geometry *ge
   for (int f = 0; f < 6; ++f)
     if (mesh->bc[f] != DG_BC_DIRICHLET && mesh->bc[f] != DG_BC_NEUMANN) return fail(DG_ERR_ARG, "bad bc");
   if (geom->map != DG_MAP_AFFINE && geom->map != DG_MAP_SINE) return fail(DG_ERR_ARG, "bad map");
-  if (geom->storage != DG_STORE_JACOBIAN && geom->storage != DG_STORE_MERGED)
+  if (geom->storage != DG_STORE_JACOBIAN && geom->storage != DG_STORE_MERGED && geom->storage != DG_STORE_MIXED)
     return fail(DG_ERR_ARG, "bad geometry storage");
   if (coef->kind != DG_COEF_CONST && coef->kind != DG_COEF_SINCOS) return fail(DG_ERR_ARG, "bad coefficient");
   if (precisions == 0 || (precisions & ~3u)) return fail(DG_ERR_ARG, "precisions must be a nonempty subset of F64|F32");
@@ -618,9 +625,8 @@ dg_status dg_footprint(const dg_mesh *mesh, int degree, const dg_geometry *geom,
   dg_status st = validate(mesh, degree, geom, coef, precisions);
   if (st != DG_OK) return st;
   if (!bytes) return fail(DG_ERR_ARG, "bytes is null");
-  const int gk = geom_kind(geom, coef);
   const int64_t nc[3] = {mesh->ncell[0], mesh->ncell[1], mesh->ncell[2]};
-  *bytes = footprint_bytes(nc, degree + 1, gk, precisions);
+  *bytes = footprint_bytes(nc, degree + 1, geom_kind(geom, coef), geom_kind(geom, coef, true), precisions);
   return DG_OK;
 }
 
@@ -633,7 +639,7 @@ dg_status dg_footprint_advection(const dg_mesh *mesh, int degree, const dg_geome
   if (!vel || (vel->kind != DG_VEL_CONST && vel->kind != DG_VEL_ROTATION)) return fail(DG_ERR_ARG, "bad velocity");
   if (!bytes) return fail(DG_ERR_ARG, "bytes is null");
   const int64_t nc[3] = {mesh->ncell[0], mesh->ncell[1], mesh->ncell[2]};
-  *bytes = footprint_bytes(nc, degree + 1, ADVECTION, precisions) -
+  *bytes = footprint_bytes(nc, degree + 1, ADVECTION, ADVECTION, precisions) -
            (size_t)(nc[0] * nc[1] * nc[2]) * (degree + 1) * (degree + 1) * (degree + 1) *
                (((precisions & DG_PREC_F64) ? 8 : 0) + ((precisions & DG_PREC_F32) ? 4 : 0));  // no diagonal
   return DG_OK;
@@ -679,6 +685,7 @@ static dg_status setup_impl(const dg_mesh *mesh, int degree, int basis, const dg
   op->basis = basis;
   op->precisions = precisions;
   op->gk = vel ? ADVECTION : geom_kind(geom, coef);
+  op->gk32 = vel ? ADVECTION : geom_kind(geom, coef, true);
   if (alloc) {
     op->alloc = *alloc;
     op->own_alloc = false;
@@ -708,7 +715,8 @@ static dg_status setup_impl(const dg_mesh *mesh, int degree, int basis, const dg
 
   // geometry: FP64 is always built (the diagonal is computed from it); it is
   // released again below if only FP32 was asked for
-  const int64_t ncv = geom_cell_values(op->gk), nfv = geom_face_values(op->gk);
+  // (DG_STORE_MIXED: the FP32 cell data is of another kind than the FP64 one)
+  const int64_t nfv = geom_face_values(op->gk);
   GeoArgs g = geo_args(op);
   auto cleanup = [&](dg_status e) {
     dg_destroy(op);
@@ -718,6 +726,7 @@ static dg_status setup_impl(const dg_mesh *mesh, int degree, int basis, const dg
     const bool want = (p == 0) || (precisions & DG_PREC_F32);
     if (!want) continue;
     const size_t es = p == 0 ? 8 : 4;
+    const int64_t ncv = geom_cell_values(p == 0 ? op->gk : op->gk32);
     if (ncv) {
       op->cell_geo[p] = op_alloc(op, ncv * op->ncells * n3 * es);
       if (!op->cell_geo[p]) return cleanup(fail(DG_ERR_OOM, "cell geometry allocation failed"));
@@ -728,17 +737,27 @@ static dg_status setup_impl(const dg_mesh *mesh, int degree, int basis, const dg
         if (!op->face_geo[p][a]) return cleanup(fail(DG_ERR_OOM, "face geometry allocation failed"));
       }
   }
-  if (ncv) {
+  {
     const int64_t npts = op->ncells * n3;
     const int grid = (int)((npts + 255) / 256);
+    auto cells = [&](int gk, double *o64, float *o32) {
+      if (!o64 && !o32) return;
+      if (gk == CURVED) hipLaunchKernelGGL(geom_cells_kernel<CURVED>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
+      else if (gk == CURVED_MERGED)
+        hipLaunchKernelGGL(geom_cells_kernel<CURVED_MERGED>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
+      else if (gk == ADVECTION)
+        hipLaunchKernelGGL(geom_cells_kernel<ADVECTION>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
+      else if (gk == AFFINE_VAR)
+        hipLaunchKernelGGL(geom_cells_kernel<AFFINE_VAR>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
+    };
     double *o64 = static_cast<double *>(op->cell_geo[0]);
     float *o32 = static_cast<float *>(op->cell_geo[1]);
-    if (op->gk == CURVED) hipLaunchKernelGGL(geom_cells_kernel<CURVED>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
-    else if (op->gk == CURVED_MERGED)
-      hipLaunchKernelGGL(geom_cells_kernel<CURVED_MERGED>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
-    else if (op->gk == ADVECTION)
-      hipLaunchKernelGGL(geom_cells_kernel<ADVECTION>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
-    else hipLaunchKernelGGL(geom_cells_kernel<AFFINE_VAR>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
+    if (op->gk == op->gk32) {
+      cells(op->gk, o64, o32);
+    } else {
+      cells(op->gk, o64, nullptr);
+      cells(op->gk32, nullptr, o32);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cleanup(hip_fail(e, "geometry kernel"));
   }

@@ -933,13 +933,13 @@ sipg_diag_kernel(const OpView<double> op, double *__restrict__ d64, float *__res
 
 namespace dgk {
 
-// f(gk, bs) with the op's SIPG geometry kind and basis as compile-time
-// constants (the Hermite-like basis exists from N = 4 on)
+// f(gk, bs) with the geometry kind of the op's FP64 or FP32 data and its
+// basis as compile-time constants (the Hermite-like basis exists from N = 4 on)
 template <int N, typename F>
-__host__ void sipg_variant(const dg_op *op, F &&f)
+__host__ void sipg_variant(const dg_op *op, bool f32, F &&f)
 {
   auto with_gk = [&](auto bs) {
-    switch (op->gk) {
+    switch (f32 ? op->gk32 : op->gk) {
       case CURVED: f(std::integral_constant<int, CURVED>{}, bs); break;
       case CURVED_MERGED: f(std::integral_constant<int, CURVED_MERGED>{}, bs); break;
       case AFFINE_VAR: f(std::integral_constant<int, AFFINE_VAR>{}, bs); break;
@@ -969,7 +969,7 @@ hipError_t launch_apply(const dg_op *op, const void *src, void *dst, bool f32, h
       hipLaunchKernelGGL((adv_apply_kernel<N, Real>), dim3(grid), dim3(BK::TPB), 0, s, view, x, y);
       return;
     }
-    sipg_variant<N>(op, [&](auto gk, auto bs) {
+    sipg_variant<N>(op, f32, [&](auto gk, auto bs) {
       hipLaunchKernelGGL((sipg_apply_kernel<N, Real, decltype(gk)::value, false, decltype(bs)::value>), dim3(grid),
                          dim3(BK::TPB), 0, s, view, x, y, DotOut<Real>{});
     });
@@ -992,7 +992,7 @@ hipError_t launch_apply_dot(const dg_op *op, const void *src, void *dst, bool f3
     const Real *x = static_cast<const Real *>(src);
     Real *y = static_cast<Real *>(dst);
     DotOut<Real> d{static_cast<Real *>(part)};
-    sipg_variant<N>(op, [&](auto gk, auto bs) {
+    sipg_variant<N>(op, f32, [&](auto gk, auto bs) {
       hipLaunchKernelGGL((sipg_apply_kernel<N, Real, decltype(gk)::value, true, decltype(bs)::value>), dim3(grid),
                          dim3(BK::TPB), 0, s, view, x, y, d);
     });
@@ -1017,7 +1017,7 @@ hipError_t launch_diag(const dg_op *op, void *diag64, void *diag32, hipStream_t 
   if (grid == 0) return hipSuccess;
   double *d64 = static_cast<double *>(diag64);
   float *d32 = static_cast<float *>(diag32);
-  sipg_variant<N>(op, [&](auto gk, auto bs) {
+  sipg_variant<N>(op, false, [&](auto gk, auto bs) {
     hipLaunchKernelGGL((sipg_diag_kernel<N, decltype(gk)::value, decltype(bs)::value>), dim3(grid), dim3(block), 0, s,
                        op->v64, d64, d32);
   });

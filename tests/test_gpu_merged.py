@@ -110,3 +110,48 @@ def test_merged_mixed_solve(dg):
     assert float(torch.linalg.norm(xa - xb) / torch.linalg.norm(xa)) <= 1e-8
     a.close()
     b.close()
+
+
+def test_mixed_storage_is_g3_in_fp64_and_g4_in_fp32(dg):
+    """DG_STORE_MIXED: FP64 applies bitwise those of the stored-Jacobian op,
+    FP32 applies bitwise those of the merged op; the diagonal is the G3 one."""
+    import torch
+    kw = dict(curved=True, variable_coef=True)
+    g3 = dg.Operator((6, 5, 7), 4, **kw)
+    g4 = dg.Operator((6, 5, 7), 4, merged=True, **kw)
+    mx = dg.Operator((6, 5, 7), 4, storage="mixed", **kw)
+    u = torch.from_numpy(synth.src_vector(g3.n_dofs, 41)).cuda()
+    assert torch.equal(mx.apply(u), g3.apply(u))
+    u32 = u.float()
+    assert torch.equal(mx.apply(u32), g4.apply(u32))
+    assert torch.equal(mx.diagonal(torch.float64), g3.diagonal(torch.float64))
+    assert torch.equal(mx.diagonal(torch.float32), g3.diagonal(torch.float32))
+    for op in (g3, g4, mx):
+        op.close()
+
+
+def test_mixed_storage_solves(dg):
+    """Mixed-precision refinement on the mixed storage (FP32 inner solver on
+    the merged coefficient, FP64 residuals on the stored Jacobians) reaches
+    the FP64 tolerance and the G3 solution; the batch serves it too."""
+    import torch
+    kw = dict(curved=True, variable_coef=True)
+    a = dg.Operator(8, 5, **kw)
+    b = dg.Operator(8, 5, storage="mixed", **kw)
+    rhs = a.rhs()
+    xa, sa = a.cg_solve(rhs, mode=0, rel_tol=1e-10)
+    xb, sb = b.cg_solve(rhs, mode=2, rel_tol=1e-10)
+    assert sa["converged"] and sb["converged"] and sb["final_rel_residual"] <= 1e-10
+    assert float(torch.linalg.norm(xa - xb) / torch.linalg.norm(xa)) <= 1e-8
+    batch = dg.Batch(2)
+    x = torch.zeros_like(rhs)
+    batch.admit(b, rhs, x, rel_tol=1e-10)
+    out = []
+    while batch.active:
+        batch.run(20)
+        out += batch.poll()
+    batch.close()
+    assert out[0][1]["final_rel_residual"] <= 1e-10
+    assert float(torch.linalg.norm(x - xa) / torch.linalg.norm(xa)) <= 1e-8
+    a.close()
+    b.close()

@@ -176,3 +176,17 @@ def test_bad_basis_rejected(dg):
         dg.basis_tables(2, "hermite")
     with pytest.raises(ValueError):
         dg.basis_tables(3, "legendre")
+
+
+def test_footprint_mixed_storage(dg):
+    # G3 (10 values) in FP64, G4 (6 values) in FP32; faces (4 values) and the diagonal in both
+    k, N = 4, 32
+    n = k + 1
+    cells = N ** 3
+    faces = 3 * N * N * (N + 1)
+    f64 = (10 * cells * n ** 3 + 4 * faces * n ** 2 + cells * n ** 3) * 8
+    f32 = (6 * cells * n ** 3 + 4 * faces * n ** 2 + cells * n ** 3) * 4
+    assert dg.footprint(N, k, curved=True, storage="mixed") == f64 + f32
+    assert dg.footprint(N, k, curved=True, storage="mixed", precisions=dg.PREC_F32) == f32
+    with pytest.raises(ValueError):
+        dg.footprint(N, k, curved=True, storage="packed")
