@@ -7,7 +7,10 @@ solution and solver workspace) fits in the budget next to the requests
 already resident; its operator is then built on the GPU and its solve joins
 the batch.  The loop advances all resident solves together a few CG
 iterations at a time and retires finished ones as they complete.  Latency is
-completion time minus arrival time.
+completion time minus arrival time.  Curved operators keep the stored
+Jacobians for their FP64 residuals and the merged coefficient for the FP32
+inner solver (the mixed geometry storage), which is the cheaper resident
+footprint and the faster inner apply.
 """
 from __future__ import annotations
 
@@ -22,11 +25,13 @@ from . import Batch, Operator, footprint
 # residual (8 B each) and the FP32 correction, residual, direction and
 # product vectors (4 B each)
 WORKSPACE_BYTES_PER_DOF = 3 * 8 + 4 * 4
+STORAGE = "mixed"
 
 
 def request_bytes(req):
     n = req["ncell"][0] * req["ncell"][1] * req["ncell"][2] * (req["degree"] + 1) ** 3
-    return footprint(req["ncell"], req["degree"], curved=req["curved"]) + WORKSPACE_BYTES_PER_DOF * n, n
+    return (footprint(req["ncell"], req["degree"], curved=req["curved"], storage=STORAGE)
+            + WORKSPACE_BYTES_PER_DOF * n, n)
 
 
 def serve(trace, *, budget_bytes, max_slots=32, rounds_per_step=10, rel_tol=1e-8, time_limit=None, log=None):
@@ -55,7 +60,7 @@ def serve(trace, *, budget_bytes, max_slots=32, rounds_per_step=10, rel_tol=1e-8
                 if used + need > budget_bytes:
                     break                        # wait for memory (FIFO)
                 waiting.popleft()
-                op = Operator(req["ncell"], req["degree"], curved=req["curved"])
+                op = Operator(req["ncell"], req["degree"], curved=req["curved"], storage=STORAGE)
                 g = torch.Generator(device="cuda")
                 g.manual_seed(req["rhs_seed"])
                 b = torch.rand(op.n_dofs, dtype=torch.float64, device="cuda", generator=g) * 2.0 - 1.0
