@@ -920,8 +920,8 @@ dg_status dg_error_manufactured(dg_op *op, dg_vec x, void *stream, double err[2]
   if (!err) return fail(DG_ERR_ARG, "err is null");
   hipStream_t s = static_cast<hipStream_t>(stream);
   GeoArgs g = geo_args(op);
-  double *part = nullptr;
-  DG_HIP(hipMalloc(&part, sizeof(double) * 2 * op->ncells));
+  double *part = static_cast<double *>(op_alloc(op, sizeof(double) * 2 * op->ncells));
+  if (!part) return fail(DG_ERR_OOM, "error workspace allocation failed");
   const double *xp = static_cast<const double *>(x.data);
   const int grid = (int)op->ncells;
   // M = N + 2 points per direction; the block is the power of two >= M^3
@@ -954,8 +954,12 @@ dg_status dg_error_manufactured(dg_op *op, dg_vec x, void *stream, double err[2]
   std::vector<double> h(2 * op->ncells);
   if (e == hipSuccess) e = hipMemcpyAsync(h.data(), part, sizeof(double) * 2 * op->ncells, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(part);
-  if (e != hipSuccess) return hip_fail(e, "error kernel");
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(s);  // the kernel may still read part
+    op_free(op, part);
+    return hip_fail(e, "error kernel");
+  }
+  op_free(op, part);
   double s0 = 0.0, s1 = 0.0;
   for (int64_t c = 0; c < op->ncells; ++c) {
     s0 += h[2 * c];
