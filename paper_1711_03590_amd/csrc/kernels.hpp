@@ -445,22 +445,26 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
       }
       jump[s] = um[s] - up;
       dsum[s] = dm[s] + dp;
-      V[s * N2 + l] = interior[s] ? um[s] + up : Real(2) * um[s];
+      if constexpr (curved_faces(GK)) V[s * N2 + l] = interior[s] ? um[s] + up : Real(2) * um[s];
     }
   }
   __syncthreads();
-  // S5: tangential collocation derivatives of V (lines along t1 and t2)
-  for_jobs<N, 4 * N>(l, act, [&](int jb) {
-    const int s = jb / (2 * N), c = (jb / N) & 1, i = jb % N;
-    const int base = c ? i : N * i, stride = c ? N : 1;
-    Real v[N], r[N];
+  // S5: tangential collocation derivatives of V (lines along t1 and t2).
+  // On affine meshes j is normal to the face, so the tangential gradient and
+  // the tangential gradient-test terms (S5, S7) drop out exactly.
+  if constexpr (curved_faces(GK)) {
+    for_jobs<N, 4 * N>(l, act, [&](int jb) {
+      const int s = jb / (2 * N), c = (jb / N) & 1, i = jb % N;
+      const int base = c ? i : N * i, stride = c ? N : 1;
+      Real v[N], r[N];
 #pragma unroll
-    for (int m = 0; m < N; ++m) v[m] = V[s * N2 + base + m * stride];
-    eo_apply<N, M_DCO>(v, r);
+      for (int m = 0; m < N; ++m) v[m] = V[s * N2 + base + m * stride];
+      eo_apply<N, M_DCO>(v, r);
 #pragma unroll
-    for (int m = 0; m < N; ++m) dV[(2 * s + c) * N2 + base + m * stride] = r[m];
-  });
-  __syncthreads();
+      for (int m = 0; m < N; ++m) dV[(2 * s + c) * N2 + base + m * stride] = r[m];
+    });
+    __syncthreads();
+  }
   // S6: numerical flux at this face point (Algorithm 1 step (c) for faces)
   Real tv[2] = {Real(0), Real(0)}, tga[2] = {Real(0), Real(0)};
   if (act) {
@@ -469,31 +473,37 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
       const Real c_ds = (!interior[s] && op.bc[2 * A + s] != 0) ? Real(0) : cds[s];  // Neumann: nothing
       const Real sg = s ? Real(1) : Real(-1);
       const Real je[3] = {sg * jg[s][0], sg * jg[s][1], sg * jg[s][2]};
-      Real g[3];
-      g[t1] = dV[(2 * s) * N2 + l];
-      g[t2] = dV[(2 * s + 1) * N2 + l];
-      g[A] = dsum[s];
-      const Real avg = Real(0.5) * (je[0] * g[0] + je[1] * g[1] + je[2] * g[2]);
-      tv[s] = c_ds * (op.tau[A] * jump[s] - avg);
       const Real gfac = Real(-0.5) * c_ds * jump[s];
       tga[s] = gfac * je[A];
-      Z[(2 * s) * N2 + l] = gfac * je[t1];
-      Z[(2 * s + 1) * N2 + l] = gfac * je[t2];
+      if constexpr (curved_faces(GK)) {
+        Real g[3];
+        g[t1] = dV[(2 * s) * N2 + l];
+        g[t2] = dV[(2 * s + 1) * N2 + l];
+        g[A] = dsum[s];
+        const Real avg = Real(0.5) * (je[0] * g[0] + je[1] * g[1] + je[2] * g[2]);
+        tv[s] = c_ds * (op.tau[A] * jump[s] - avg);
+        Z[(2 * s) * N2 + l] = gfac * je[t1];
+        Z[(2 * s + 1) * N2 + l] = gfac * je[t2];
+      } else {
+        tv[s] = c_ds * (op.tau[A] * jump[s] - Real(0.5) * (je[A] * dsum[s]));
+      }
     }
   }
-  __syncthreads();
   // S7: transposed tangential collocation derivatives of the gradient-test terms
-  for_jobs<N, 4 * N>(l, act, [&](int jb) {
-    const int s = jb / (2 * N), c = (jb / N) & 1, i = jb % N;
-    const int base = c ? i : N * i, stride = c ? N : 1;
-    Real v[N], r[N];
+  if constexpr (curved_faces(GK)) {
+    __syncthreads();
+    for_jobs<N, 4 * N>(l, act, [&](int jb) {
+      const int s = jb / (2 * N), c = (jb / N) & 1, i = jb % N;
+      const int base = c ? i : N * i, stride = c ? N : 1;
+      Real v[N], r[N];
 #pragma unroll
-    for (int m = 0; m < N; ++m) v[m] = Z[(2 * s + c) * N2 + base + m * stride];
-    eo_apply<N, M_DCOT>(v, r);
+      for (int m = 0; m < N; ++m) v[m] = Z[(2 * s + c) * N2 + base + m * stride];
+      eo_apply<N, M_DCOT>(v, r);
 #pragma unroll
-    for (int m = 0; m < N; ++m) Z2[(2 * s + c) * N2 + base + m * stride] = r[m];
-  });
-  __syncthreads();
+      for (int m = 0; m < N; ++m) Z2[(2 * s + c) * N2 + base + m * stride] = r[m];
+    });
+    __syncthreads();
+  }
   // S8: face-normal integration onto this thread's normal line of R: the
   // rank-4 update L0 w0 + dL0 tga0 + L1 w1 + dL1 tga1.  The first direction
   // initialises R, the second adds to it, and the third hands its four
@@ -502,7 +512,10 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
   if (act) {
     Real w[2];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) w[s] = tv[s] + Z2[(2 * s) * N2 + l] + Z2[(2 * s + 1) * N2 + l];
+    for (int s = 0; s < 2; ++s) {
+      w[s] = tv[s];
+      if constexpr (curved_faces(GK)) w[s] += Z2[(2 * s) * N2 + l] + Z2[(2 * s + 1) * N2 + l];
+    }
     if constexpr (A == 2) {
       fz[0] = w[0];
       fz[1] = tga[0];
