@@ -650,100 +650,137 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
   for (int k = PRE; k < NB; ++k) load_geometry(k, gbuf[k]);
   __syncthreads();  // the z faces' Z2 reads are done before W takes the gradients
 
-  // (d) cell integrals: collocation derivatives along x and y (z is taken
-  // in registers below), then the quadrature-point operation along this
-  // thread's z-line with the stored geometry (J^{-T} and c det J w per
-  // point) software-pipelined NB planes ahead, then the transposed
-  // derivatives, all summed into R
-  if (act) {
-    sweep<N, 0, M_DCO>(Q, G0, l);
-    sweep<N, 1, M_DCO>(Q, G1, l);
-  }
-  __syncthreads();
-  if (act) {
-    Real qz[N], dz[N], t2v[N];
-    load_line<N, 2>(Q, l, qz);
-    eo_apply<N, M_DCO>(qz, dz);
+  if constexpr (!curved_faces(GK)) {
+    // (d) affine cell integrals: J^{-1} is diagonal, so the cell term splits
+    // by direction, R += sum_d Dco_d^T (f h_d^{-2} Dco_d Q) with f = c det J w
+    // per point: one line pass per direction, the z pass also taking the z
+    // faces' normal integration
+    const int i1 = l % N, i2 = l / N;
+    Real w1 = Real(0), w2 = Real(0);  // weights of this thread's fixed indices
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-      const int p = l + k * N2;
-      const Real g[3] = {G0[p], G1[p], dz[k]};
-      Real o[3];
-      if constexpr (GK == CURVED) {
-        const Real *jt = gbuf[k % NB];
-        const Real f = gbuf[k % NB][9];
-        Real gx[3];
+    for (int q = 0; q < N; ++q) {
+      if (q == i1) w1 = Real(T.gw[q]);
+      if (q == i2) w2 = Real(T.gw[q]);
+    }
+    auto pass = [&](auto dir) {
+      constexpr int D = decltype(dir)::value;
+      if (act) {
+        Real v[N], g[N], r[N], q[N];
+        load_line<N, D>(Q, l, v);
+        eo_apply<N, M_DCO>(v, g);
+        const Real ih2 = op.inv_h[D] * op.inv_h[D];
+        const int b = line_base<N, D>(l);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) gx[a] = f * (jt[3 * a] * g[0] + jt[3 * a + 1] * g[1] + jt[3 * a + 2] * g[2]);
-#pragma unroll
-        for (int b = 0; b < 3; ++b) o[b] = jt[b] * gx[0] + jt[3 + b] * gx[1] + jt[6 + b] * gx[2];
-        __builtin_amdgcn_sched_barrier(0);
-        if (k + NB < N) load_geometry(k + NB, gbuf[k % NB]);
-      } else if constexpr (GK == CURVED_MERGED) {
-        // G4: t = M grad_xi u with the symmetric M = c det J w J^{-1} J^{-T}
-        const Real *M = gbuf[k % NB];
-        o[0] = M[0] * g[0] + M[1] * g[1] + M[2] * g[2];
-        o[1] = M[1] * g[0] + M[3] * g[1] + M[4] * g[2];
-        o[2] = M[2] * g[0] + M[4] * g[1] + M[5] * g[2];
-        __builtin_amdgcn_sched_barrier(0);
-        if (k + NB < N) load_geometry(k + NB, gbuf[k % NB]);
-      } else {
-        Real f;
-        if constexpr (GK == AFFINE_VAR) {
-          f = op.g.cell[(int64_t)cell * N3 + p];
-        } else {
-          const int i1 = l % N, i2 = l / N;
-          Real w1 = Real(0), w2 = Real(0);
-#pragma unroll
-          for (int q = 0; q < N; ++q) {
-            if (q == i1) w1 = Real(T.gw[q]);
-            if (q == i2) w2 = Real(T.gw[q]);
+        for (int m = 0; m < N; ++m) {
+          Real f;
+          if constexpr (GK == AFFINE_VAR) {
+            f = op.g.cell[(int64_t)cell * N3 + b + m * kStride<N, D>];
+          } else {
+            // the line's own direction is D; l holds the other two indices in increasing order
+            f = op.c_vol * w1 * w2 * Real(T.gw[m]);
           }
-          f = op.c_vol * w1 * w2 * Real(T.gw[k]);
+          g[m] *= f * ih2;
         }
+        eo_apply<N, M_DCOT>(g, r);
+        load_line<N, D>(R, l, q);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) o[a] = f * op.inv_h[a] * op.inv_h[a] * g[a];
+        for (int m = 0; m < N; ++m) {
+          Real x = q[m] + r[m];
+          if constexpr (D == 2) {
+            x = madd(T.L0[m], fz[0], x);
+            x = fma(Real(T.dL0[m]), fz[1], x);
+            x = madd(T.L1[m], fz[2], x);
+            x = fma(Real(T.dL1[m]), fz[3], x);
+          }
+          q[m] = x;
+        }
+        store_line<N, D>(R, l, q);
       }
-      G0[p] = o[0];
-      G1[p] = o[1];
-      t2v[k] = o[2];
+      __syncthreads();
+    };
+    pass(std::integral_constant<int, 0>{});
+    pass(std::integral_constant<int, 1>{});
+    pass(std::integral_constant<int, 2>{});
+  } else {
+    // (d) cell integrals: collocation derivatives along x and y (z is taken
+    // in registers below), then the quadrature-point operation along this
+    // thread's z-line with the stored geometry (J^{-T} and c det J w per
+    // point) software-pipelined NB planes ahead, then the transposed
+    // derivatives, all summed into R
+    if (act) {
+      sweep<N, 0, M_DCO>(Q, G0, l);
+      sweep<N, 1, M_DCO>(Q, G1, l);
     }
-    Real rz[N], q[N];
-    eo_apply<N, M_DCOT>(t2v, rz);
-    load_line<N, 2>(R, l, q);
-    // plus the z faces' normal integration onto the same line
+    __syncthreads();
+    if (act) {
+      Real qz[N], dz[N], t2v[N];
+      load_line<N, 2>(Q, l, qz);
+      eo_apply<N, M_DCO>(qz, dz);
 #pragma unroll
-    for (int m = 0; m < N; ++m) {
-      Real v = q[m] + rz[m];
-      v = madd(T.L0[m], fz[0], v);
-      v = fma(Real(T.dL0[m]), fz[1], v);
-      v = madd(T.L1[m], fz[2], v);
-      v = fma(Real(T.dL1[m]), fz[3], v);
-      q[m] = v;
+      for (int k = 0; k < N; ++k) {
+        const int p = l + k * N2;
+        const Real g[3] = {G0[p], G1[p], dz[k]};
+        Real o[3];
+        if constexpr (GK == CURVED) {
+          const Real *jt = gbuf[k % NB];
+          const Real f = gbuf[k % NB][9];
+          Real gx[3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) gx[a] = f * (jt[3 * a] * g[0] + jt[3 * a + 1] * g[1] + jt[3 * a + 2] * g[2]);
+#pragma unroll
+          for (int b = 0; b < 3; ++b) o[b] = jt[b] * gx[0] + jt[3 + b] * gx[1] + jt[6 + b] * gx[2];
+          __builtin_amdgcn_sched_barrier(0);
+          if (k + NB < N) load_geometry(k + NB, gbuf[k % NB]);
+        } else if constexpr (GK == CURVED_MERGED) {
+          // G4: t = M grad_xi u with the symmetric M = c det J w J^{-1} J^{-T}
+          const Real *M = gbuf[k % NB];
+          o[0] = M[0] * g[0] + M[1] * g[1] + M[2] * g[2];
+          o[1] = M[1] * g[0] + M[3] * g[1] + M[4] * g[2];
+          o[2] = M[2] * g[0] + M[4] * g[1] + M[5] * g[2];
+          __builtin_amdgcn_sched_barrier(0);
+          if (k + NB < N) load_geometry(k + NB, gbuf[k % NB]);
+        }
+        G0[p] = o[0];
+        G1[p] = o[1];
+        t2v[k] = o[2];
+      }
+      Real rz[N], q[N];
+      eo_apply<N, M_DCOT>(t2v, rz);
+      load_line<N, 2>(R, l, q);
+      // plus the z faces' normal integration onto the same line
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        Real v = q[m] + rz[m];
+        v = madd(T.L0[m], fz[0], v);
+        v = fma(Real(T.dL0[m]), fz[1], v);
+        v = madd(T.L1[m], fz[2], v);
+        v = fma(Real(T.dL1[m]), fz[3], v);
+        q[m] = v;
+      }
+      store_line<N, 2>(R, l, q);
     }
-    store_line<N, 2>(R, l, q);
-  }
-  __syncthreads();
-  if (act) {
-    Real v[N], r[N], q[N];
-    load_line<N, 0>(G0, l, v);
-    eo_apply<N, M_DCOT>(v, r);
-    load_line<N, 0>(R, l, q);
+    __syncthreads();
+    if (act) {
+      Real v[N], r[N], q[N];
+      load_line<N, 0>(G0, l, v);
+      eo_apply<N, M_DCOT>(v, r);
+      load_line<N, 0>(R, l, q);
 #pragma unroll
-    for (int m = 0; m < N; ++m) q[m] += r[m];
-    store_line<N, 0>(R, l, q);
-  }
-  __syncthreads();
-  if (act) {
-    Real v[N], r[N], q[N];
-    load_line<N, 1>(G1, l, v);
-    eo_apply<N, M_DCOT>(v, r);
-    load_line<N, 1>(R, l, q);
+      for (int m = 0; m < N; ++m) q[m] += r[m];
+      store_line<N, 0>(R, l, q);
+    }
+    __syncthreads();
+    if (act) {
+      Real v[N], r[N], q[N];
+      load_line<N, 1>(G1, l, v);
+      eo_apply<N, M_DCOT>(v, r);
+      load_line<N, 1>(R, l, q);
 #pragma unroll
-    for (int m = 0; m < N; ++m) q[m] += r[m];
-    store_line<N, 1>(R, l, q);
+      for (int m = 0; m < N; ++m) q[m] += r[m];
+      store_line<N, 1>(R, l, q);
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
   // (e) back to the Gauss-Lobatto basis (transposed basis change) and write
   if (act) sweep<N, 0, kMST<BS>>(R, R, l);
