@@ -122,16 +122,16 @@ __global__ void __launch_bounds__(kRedThreads) batch_update_kernel(const BatchSl
 {
   __shared__ float sh[kRedThreads];
   const BatchSlot &sl = slots[blockIdx.x / kRedBlocks];
-  cg_update_body<float, float>(sl.e, sl.r, sl.p, sl.q, sl.d, sl.ndofs, sl.part, sl.part + 3 * kRedBlocks,
-                               batch_cur(sl, round), sl.part + kRedBlocks, blockIdx.x % kRedBlocks, sh);
+  cg_update_body<float, float>(sl.r, sl.q, sl.d, sl.ndofs, sl.part, sl.part + 3 * kRedBlocks, batch_cur(sl, round),
+                               sl.part + kRedBlocks, blockIdx.x % kRedBlocks, sh);
 }
 
 __global__ void __launch_bounds__(kRedThreads) batch_pupdate_kernel(const BatchSlot *__restrict__ slots, int round)
 {
   __shared__ float sh[kRedThreads];
   const BatchSlot &sl = slots[blockIdx.x / kRedBlocks];
-  cg_pupdate_body<float, float>(sl.p, sl.r, sl.d, sl.ndofs, sl.part + kRedBlocks, sl.part + 3 * kRedBlocks, 1,
-                                batch_cur(sl, round), blockIdx.x % kRedBlocks, sh);
+  cg_pupdate_body<float, float>(sl.p, sl.e, sl.r, sl.d, sl.ndofs, sl.part, sl.part + kRedBlocks,
+                                sl.part + 3 * kRedBlocks, 1, batch_cur(sl, round), blockIdx.x % kRedBlocks, sh);
 }
 
 // r.r of every request into one array (one read-back per check)

@@ -128,8 +128,8 @@ dg_status pcg(dg_op *op, const Real *rhs, Real *x, bool x_zero, double tol_abs, 
   }
   // z = r / d, p = z, rz = r.z, rr = r.r
   hipLaunchKernelGGL((rz_partial_kernel<Real, Acc>), dim3(grid), dim3(kRedThreads), 0, s, r, d, n, rz_part);
-  hipLaunchKernelGGL((cg_pupdate_kernel<Real, Acc>), dim3(grid), dim3(kRedThreads), 0, s, p, r, d, n, rz_part,
-                     scal, 0, 0);
+  hipLaunchKernelGGL((cg_pupdate_kernel<Real, Acc>), dim3(grid), dim3(kRedThreads), 0, s, p, (Real *)nullptr, r, d, n,
+                     pq_part, rz_part, scal, 0, 0);
   DG_HIP(hipGetLastError());
   int par = 1;  // scal[par] holds the current r.z
   int it = 0;
@@ -146,10 +146,10 @@ dg_status pcg(dg_op *op, const Real *rhs, Real *x, bool x_zero, double tol_abs, 
   if (!(rn > tol_abs)) done = true;
   while (!done && it < max_iter) {
     DG_HIP(buf.apply_dot(op, p, q, s));
-    hipLaunchKernelGGL((cg_update_kernel<Real, Acc>), dim3(grid), dim3(kRedThreads), 0, s, x, r, p, q, d, n,
-                       pq_part, scal, par, rz_part);
-    hipLaunchKernelGGL((cg_pupdate_kernel<Real, Acc>), dim3(grid), dim3(kRedThreads), 0, s, p, r, d, n, rz_part,
-                       scal, 1, par);
+    hipLaunchKernelGGL((cg_update_kernel<Real, Acc>), dim3(grid), dim3(kRedThreads), 0, s, r, q, d, n, pq_part, scal,
+                       par, rz_part);
+    hipLaunchKernelGGL((cg_pupdate_kernel<Real, Acc>), dim3(grid), dim3(kRedThreads), 0, s, p, x, r, d, n, pq_part,
+                       rz_part, scal, 1, par);
     DG_HIP(hipGetLastError());
     par = 1 - par;
     ++it;
@@ -209,10 +209,10 @@ dg_status pcg_reliable(dg_op *op, const double *b, double *x, double nb, double 
   st.iters_outer = 1;
   for (int it = 1; it <= max_iter; ++it) {
     DG_HIP(buf.apply_dot(op, p, q, s));
-    hipLaunchKernelGGL((cg_update_kernel<float, float>), dim3(grid), dim3(kRedThreads), 0, s, e, r, p, q, d, n,
-                       pq_part, scal, par, rz_part);
-    hipLaunchKernelGGL((cg_pupdate_kernel<float, float>), dim3(grid), dim3(kRedThreads), 0, s, p, r, d, n, rz_part,
-                       scal, 1, par);
+    hipLaunchKernelGGL((cg_update_kernel<float, float>), dim3(grid), dim3(kRedThreads), 0, s, r, q, d, n, pq_part,
+                       scal, par, rz_part);
+    hipLaunchKernelGGL((cg_pupdate_kernel<float, float>), dim3(grid), dim3(kRedThreads), 0, s, p, e, r, d, n, pq_part,
+                       rz_part, scal, 1, par);
     DG_HIP(hipGetLastError());
     par = 1 - par;
     st.iters_inner += 1;

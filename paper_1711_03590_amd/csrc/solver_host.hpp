@@ -32,8 +32,8 @@ inline hipError_t start_direction_async(int64_t n, float *e, const float *r, flo
   float *rz_part = part + kRedBlocks, *scal = part + 3 * kRedBlocks;
   hipLaunchKernelGGL((fill_kernel<float>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, e, 0.0f, n);
   hipLaunchKernelGGL((rz_partial_kernel<float, float>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, r, d, n, rz_part);
-  hipLaunchKernelGGL((cg_pupdate_kernel<float, float>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, p, r, d, n,
-                     rz_part, scal, 0, 0);
+  hipLaunchKernelGGL((cg_pupdate_kernel<float, float>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, p,
+                     (float *)nullptr, r, d, n, part, rz_part, scal, 0, 0);
   return hipGetLastError();
 }
 

@@ -173,10 +173,11 @@ __global__ void __launch_bounds__(kRedThreads) rz_partial_kernel(const Real *__r
   }
 }
 
-// alpha = rz / (p.q);  x += alpha p;  r -= alpha q;  partials of r.z, r.r
+// alpha = rz / (p.q);  r -= alpha q;  partials of r.z, r.r (the solution
+// update x += alpha p is left to the direction update, which reads p anyway)
 template <typename Real, typename Acc>
-__device__ __forceinline__ void cg_update_body(Real *__restrict__ x, Real *__restrict__ r, const Real *__restrict__ p,
-                                               const Real *__restrict__ q, const Real *__restrict__ d, int64_t n,
+__device__ __forceinline__ void cg_update_body(Real *__restrict__ r, const Real *__restrict__ q,
+                                               const Real *__restrict__ d, int64_t n,
                                                const Acc *__restrict__ pq_part, const Acc *scal, int cur,
                                                Acc *__restrict__ part2, int chunk, Acc *sh)
 {
@@ -187,8 +188,7 @@ __device__ __forceinline__ void cg_update_body(Real *__restrict__ x, Real *__res
   const Acc pq = reduce_partials(pq_part, 1, sh);
   const Acc alpha = scal[cur] / pq;
   Acc rz = Acc(0), rr = Acc(0);
-  auto one = [&](int64_t j, Real xv, Real pv, Real rv, Real qv, Real dv) {
-    x[j] = (Real)((Acc)xv + alpha * (Acc)pv);
+  auto one = [&](int64_t j, Real rv, Real qv, Real dv) {
     const Acc ri = (Acc)rv - alpha * (Acc)qv;
     r[j] = (Real)ri;
     rz += ri * (ri / (Acc)dv);
@@ -196,20 +196,18 @@ __device__ __forceinline__ void cg_update_body(Real *__restrict__ x, Real *__res
   };
   int64_t i = (int64_t)chunk * kRedThreads + threadIdx.x;
   for (; i + (kUnroll - 1) * kChunkStride < n; i += kUnroll * kChunkStride) {
-    Real xv[kUnroll], pv[kUnroll], rv[kUnroll], qv[kUnroll], dv[kUnroll];
+    Real rv[kUnroll], qv[kUnroll], dv[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int64_t j = i + u * kChunkStride;
-      xv[u] = x[j];
-      pv[u] = p[j];
       rv[u] = r[j];
       qv[u] = q[j];
       dv[u] = d[j];
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) one(i + u * kChunkStride, xv[u], pv[u], rv[u], qv[u], dv[u]);
+    for (int u = 0; u < kUnroll; ++u) one(i + u * kChunkStride, rv[u], qv[u], dv[u]);
   }
-  for (; i < n; i += kChunkStride) one(i, x[i], p[i], r[i], q[i], d[i]);
+  for (; i < n; i += kChunkStride) one(i, r[i], q[i], d[i]);
   rz = block_sum(rz, sh);
   rr = block_sum(rr, sh);
   if (threadIdx.x == 0) {
@@ -219,47 +217,77 @@ __device__ __forceinline__ void cg_update_body(Real *__restrict__ x, Real *__res
 }
 
 template <typename Real, typename Acc>
-__global__ void __launch_bounds__(kRedThreads) cg_update_kernel(Real *__restrict__ x, Real *__restrict__ r,
-                                                                const Real *__restrict__ p, const Real *__restrict__ q,
+__global__ void __launch_bounds__(kRedThreads) cg_update_kernel(Real *__restrict__ r, const Real *__restrict__ q,
                                                                 const Real *__restrict__ d, int64_t n,
                                                                 const Acc *__restrict__ pq_part, const Acc *scal,
                                                                 int cur, Acc *__restrict__ part2)
 {
   __shared__ Acc sh[kRedThreads];
-  cg_update_body(x, r, p, q, d, n, pq_part, scal, cur, part2, blockIdx.x, sh);
+  cg_update_body(r, q, d, n, pq_part, scal, cur, part2, blockIdx.x, sh);
 }
 
-// rz_new = r.z;  p = z + (rz_new / scal[cur]) p  (p = z when use_beta == 0);
-// chunk 0 stores rz_new in scal[1 - cur] and r.r in scal[2] (the other
-// chunks still read scal[cur], hence the ping-pong)
+// x += alpha p with the same alpha = scal[cur] / (p.q) as cg_update (when x
+// is not null), then rz_new = r.z;  p = z + (rz_new / scal[cur]) p  (p = z
+// when use_beta == 0); chunk 0 stores rz_new in scal[1 - cur] and r.r in
+// scal[2] (the other chunks still read scal[cur], hence the ping-pong)
 template <typename Real, typename Acc>
-__device__ __forceinline__ void cg_pupdate_body(Real *__restrict__ p, const Real *__restrict__ r,
-                                                const Real *__restrict__ d, int64_t n, const Acc *__restrict__ part2,
+__device__ __forceinline__ void cg_pupdate_body(Real *__restrict__ p, Real *__restrict__ x,
+                                                const Real *__restrict__ r, const Real *__restrict__ d, int64_t n,
+                                                const Acc *__restrict__ pq_part, const Acc *__restrict__ part2,
                                                 Acc *scal, int use_beta, int cur, int chunk, Acc *sh)
 {
   if (chunk > 0 && (int64_t)chunk * kRedThreads >= n) return;  // empty; chunk 0 always stores the scalars
   const Acc rz = reduce_partials(part2, 2, sh);
   const Acc rr = reduce_partials(part2 + 1, 2, sh);
   const Acc beta = use_beta ? rz / scal[cur] : Acc(0);
+  Acc alpha = Acc(0);
+  if (x) alpha = scal[cur] / reduce_partials(pq_part, 1, sh);
   int64_t i = (int64_t)chunk * kRedThreads + threadIdx.x;
-  for (; i + (kUnroll - 1) * kChunkStride < n; i += kUnroll * kChunkStride) {
-    Real rv[kUnroll], dv[kUnroll], pv[kUnroll];
+  if (x) {
+    for (; i + (kUnroll - 1) * kChunkStride < n; i += kUnroll * kChunkStride) {
+      Real rv[kUnroll], dv[kUnroll], pv[kUnroll], xv[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int64_t j = i + u * kChunkStride;
-      rv[u] = r[j];
-      dv[u] = d[j];
-      pv[u] = p[j];
-    }
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t j = i + u * kChunkStride;
+        rv[u] = r[j];
+        dv[u] = d[j];
+        pv[u] = p[j];
+        xv[u] = x[j];
+      }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const Acc z = (Acc)rv[u] / (Acc)dv[u];
-      p[i + u * kChunkStride] = use_beta ? (Real)(z + beta * (Acc)pv[u]) : (Real)z;
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t j = i + u * kChunkStride;
+        x[j] = (Real)((Acc)xv[u] + alpha * (Acc)pv[u]);
+        const Acc z = (Acc)rv[u] / (Acc)dv[u];
+        p[j] = use_beta ? (Real)(z + beta * (Acc)pv[u]) : (Real)z;
+      }
     }
-  }
-  for (; i < n; i += kChunkStride) {
-    const Acc z = (Acc)r[i] / (Acc)d[i];
-    p[i] = use_beta ? (Real)(z + beta * (Acc)p[i]) : (Real)z;
+    for (; i < n; i += kChunkStride) {
+      const Acc pv = (Acc)p[i];
+      x[i] = (Real)((Acc)x[i] + alpha * pv);
+      const Acc z = (Acc)r[i] / (Acc)d[i];
+      p[i] = use_beta ? (Real)(z + beta * pv) : (Real)z;
+    }
+  } else {
+    for (; i + (kUnroll - 1) * kChunkStride < n; i += kUnroll * kChunkStride) {
+      Real rv[kUnroll], dv[kUnroll], pv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t j = i + u * kChunkStride;
+        rv[u] = r[j];
+        dv[u] = d[j];
+        pv[u] = p[j];
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const Acc z = (Acc)rv[u] / (Acc)dv[u];
+        p[i + u * kChunkStride] = use_beta ? (Real)(z + beta * (Acc)pv[u]) : (Real)z;
+      }
+    }
+    for (; i < n; i += kChunkStride) {
+      const Acc z = (Acc)r[i] / (Acc)d[i];
+      p[i] = use_beta ? (Real)(z + beta * (Acc)p[i]) : (Real)z;
+    }
   }
   if (chunk == 0 && threadIdx.x == 0) {
     scal[1 - cur] = rz;
@@ -268,13 +296,15 @@ __device__ __forceinline__ void cg_pupdate_body(Real *__restrict__ p, const Real
 }
 
 template <typename Real, typename Acc>
-__global__ void __launch_bounds__(kRedThreads) cg_pupdate_kernel(Real *__restrict__ p, const Real *__restrict__ r,
+__global__ void __launch_bounds__(kRedThreads) cg_pupdate_kernel(Real *__restrict__ p, Real *__restrict__ x,
+                                                                 const Real *__restrict__ r,
                                                                  const Real *__restrict__ d, int64_t n,
+                                                                 const Acc *__restrict__ pq_part,
                                                                  const Acc *__restrict__ part2, Acc *scal, int use_beta,
                                                                  int cur)
 {
   __shared__ Acc sh[kRedThreads];
-  cg_pupdate_body(p, r, d, n, part2, scal, use_beta, cur, blockIdx.x, sh);
+  cg_pupdate_body(p, x, r, d, n, pq_part, part2, scal, use_beta, cur, blockIdx.x, sh);
 }
 
 // scal[cur] = r.z, scal[2] = r.r from interleaved partials
