@@ -207,12 +207,13 @@ def main():
 
     del flush
     hbm = measure_hbm(torch)
-    variants = merged = advection = hermite = None
+    variants = merged = advection = hermite = degrees = None
     if args.variants:
         merged = bench_merged(dg, torch, synth, N, k, args.steps, args.warmup, res)
         hermite = bench_hermite(dg, torch, synth, N, k, args.steps, args.warmup, res)
         advection = bench_advection(dg, torch, synth, N, k, args.steps, args.warmup)
         variants = bench_variants(dg, torch, synth, k)
+        degrees = bench_degrees(dg, torch, synth)
 
     if args.copy_calibration:
         nel = args.copy_calibration * (1 << 20) // 8
@@ -272,6 +273,8 @@ def main():
         line["advection"] = advection
     if variants:
         line["geometry_variants"] = variants
+    if degrees:
+        line["degree_sweep"] = degrees
     if solve:
         line["solve"] = solve
     if serving:
@@ -309,6 +312,31 @@ def bench_variants(dg, torch, synth, k, ncell=64, steps=30):
         out[name] = rec
     out["workload"] = (f"{ncell}^3 cells, k={k}, affine with c = 1 + 0.5 sin(pi x) cos(pi y) z vs sine-curved, "
                        "stored Jacobians (G3) and merged coefficient (G4)")
+    return out
+
+
+def bench_degrees(dg, torch, synth, ncell=32, degrees=range(2, 9), steps=50):
+    """The headline mesh (32^3 sine-curved, G3) at every degree 2..8: DoF/s
+    and the fraction of the HBM roofline, FP64 and FP32."""
+    out = {}
+    for k in degrees:
+        op = dg.Operator(ncell, k, curved=True, amplitude=synth.AMPLITUDE)
+        nd = op.n_dofs
+        src = synth.src_vector(nd, synth.seed_for(2, k))
+        rec = {"n_dofs": nd}
+        for prec in ("f64", "f32"):
+            dt = torch.float64 if prec == "f64" else torch.float32
+            x = torch.from_numpy(src).to(dtype=dt, device="cuda")
+            y = torch.empty_like(x)
+            ms = time_apply(op, x, y, steps, 5, torch)
+            bpd = algorithmic_bytes_per_dof(ncell, k, 8 if prec == "f64" else 4)
+            gbs = bpd * nd / (ms * 1e-3) / 1e9
+            rec[prec] = {"dofs_per_s": nd / (ms * 1e-3), "us": ms * 1e3, "algorithmic_bytes_per_dof": bpd,
+                         "frac": gbs / HBM_PEAK_GBS}
+            del x, y
+        op.close()
+        out[f"k{k}"] = rec
+    out["workload"] = f"{ncell}^3 sine-curved, stored Jacobians (G3), degrees {min(degrees)}..{max(degrees)}"
     return out
 
 
