@@ -145,7 +145,8 @@ dg_status dg_setup(const dg_mesh *mesh, int degree, const dg_geometry *geom,
 typedef enum { DG_BASIS_NODAL = 0, DG_BASIS_HERMITE = 1 } dg_basis;
 
 /* dg_setup in the given basis.  DG_ERR_ARG for an unknown basis or
- * DG_BASIS_HERMITE below degree 3.  Every call that takes the op (apply,
+ * DG_BASIS_HERMITE below degree 3.  The basis does not change the device
+ * footprint: dg_footprint applies as it is.  Every call that takes the op (apply,
  * diagonal, right-hand side, error, CG) works in that basis; dg_batch_admit
  * returns DG_ERR_UNSUPPORTED for a Hermite op. */
 dg_status dg_setup_basis(const dg_mesh *mesh, int degree, dg_basis basis, const dg_geometry *geom,
