@@ -22,6 +22,10 @@ Parity status per function (what pins it is in tests/test_oracle_*.py):
   with basis="hermite"          closed form, reproduction of polynomials, mirror
                                 symmetry; block rows equal the cell-wise change of
                                 basis of the nodal operator's; convergence order
+  apply with cell_geometry=     pinned: equals the map's operator on affine meshes; the
+  "positions"                   interpolated Jacobian converges to the map's at
+                                order k; symmetry, Neumann null space and the
+                                convergence order of the manufactured solve
   apply with op="advection"     pinned: constants map to the inflow flux alone and
                                 the energy identity u^T A u = upwind jump terms
                                 (affine, exact quadrature), convergence order of
@@ -61,18 +65,23 @@ class Problem(ctypes.Structure):
         ("vel", ctypes.c_int32),
         ("vel_value", ctypes.c_double * 3),
         ("basis", ctypes.c_int32),
+        ("cellgeo", ctypes.c_int32),
     ]
 
 
 def problem(ncell, degree, *, curved=False, amplitude=0.05, variable_coef=False,
             coef_value=1.0, bc=(DIRICHLET,) * 6, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
-            op="sipg", velocity="rotation", basis="gll"):
+            op="sipg", velocity="rotation", basis="gll", cell_geometry="map"):
     """op="sipg" (Sec. 2 Eq. (2)) or "advection" (Eq. (1)); for advection the
     velocity is "rotation" (1/2 - y, x - 1/2, 1/4) or a constant 3-vector.
     basis="gll" (Lagrange on the Gauss-Lobatto points) or "hermite" (the
-    Hermite-like basis, degree >= 3)."""
+    Hermite-like basis, degree >= 3).  cell_geometry="map" (the map's
+    Jacobian) or "positions" (the Jacobian of the interpolant through the
+    cell's Gauss-point positions, SIPG only)."""
     if basis not in ("gll", "hermite"):
         raise ValueError("basis is 'gll' or 'hermite'")
+    if cell_geometry not in ("map", "positions"):
+        raise ValueError("cell_geometry is 'map' or 'positions'")
     if isinstance(ncell, int):
         ncell = (ncell, ncell, ncell)
     p = Problem()
@@ -87,6 +96,7 @@ def problem(ncell, degree, *, curved=False, amplitude=0.05, variable_coef=False,
     p.coef_value = coef_value
     p.op = OP_ADVECTION if op == "advection" else OP_SIPG
     p.basis = BASIS_HERMITE if basis == "hermite" else BASIS_GLL
+    p.cellgeo = 1 if cell_geometry == "positions" else 0
     if isinstance(velocity, str):
         p.vel = VEL_ROTATION
         p.vel_value[:] = [0.0, 0.0, 0.0]
@@ -120,6 +130,7 @@ def lib():
         L.orc_apply_cells.argtypes = [pp, dp, lp, ctypes.c_int64, dp]
         L.orc_diag_cells.argtypes = [pp, lp, ctypes.c_int64, dp]
         L.orc_block_rows.argtypes = [pp, lp, ctypes.c_int64, dp]
+        L.orc_cell_jacobian.argtypes = [pp, ctypes.c_int64, ctypes.c_int, dp, dp]
         L.orc_face_point.argtypes = [pp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         L.orc_volume.argtypes = [pp, dp]
         L.orc_forcing_at.argtypes = [pp, dp]
@@ -261,6 +272,14 @@ def assemble_sparse(p):
 
 def assemble_dense(p):
     return assemble_sparse(p).toarray()
+
+
+def cell_jacobian(p, cell, q):
+    """(J the cell term uses, the map's J) at Gauss point q of cell, 3x3 each."""
+    a = np.zeros(9)
+    b = np.zeros(9)
+    _check(lib().orc_cell_jacobian(ctypes.byref(p), cell, q, _dp(a), _dp(b)), "cell_jacobian")
+    return a.reshape(3, 3), b.reshape(3, 3)
 
 
 def face_point(p, cell, face, q1, q2):

@@ -39,6 +39,16 @@
  *     (Nanson's formula ds = det J |J^{-T} e| w); the neighbour's gradient uses
  *     the neighbour's own Jacobian at the same physical point.
  *   - homogeneous Neumann faces contribute nothing.
+ *   - Cell geometry from quadrature-point positions (problem field cellgeo = 1,
+ *     SIPG only): Sec. 5 lists, as variant G2, keeping only the physical
+ *     positions of the quadrature points and computing the Jacobian from them
+ *     by a collocation derivative.  Reading: the cell term uses the Jacobian
+ *     of the tensor-product polynomial through the n^3 Gauss-point positions
+ *     (degree k per direction), evaluated at those points; the coefficient is
+ *     still c at the exact point (the interpolant passes through it).  Face
+ *     terms keep the map's own normals and area elements (the paper notes
+ *     that faces need data of their own), and so do the load vector and the
+ *     error norms.
  *   - Hermite-like basis (problem field basis = 1, degree k >= 3): the paper
  *     asks only that a face value and a face derivative each need at most two
  *     coefficients per normal line (Sec. 3, the face interpolation kernel;
@@ -97,6 +107,8 @@ typedef struct {
   int32_t vel;        /* advection velocity: 0 = constant vel_value, 1 = (1/2 - y, x - 1/2, 1/4) */
   double vel_value[3];
   int32_t basis;      /* 0 = Lagrange on the Gauss-Lobatto points, 1 = Hermite-like (k >= 3) */
+  int32_t cellgeo;    /* SIPG cell integrals: 0 = Jacobian of the map, 1 = Jacobian of its
+                         interpolant through the cell's Gauss points (positions only) */
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -329,6 +341,7 @@ static int ctx_init(orc_ctx *c, const orc_problem *P)
   if (P->op != 0 && P->op != 1) return ORC_ERR_ARG;
   if (P->vel != 0 && P->vel != 1) return ORC_ERR_ARG;
   if (P->basis != 0 && (P->basis != 1 || P->degree < 3)) return ORC_ERR_ARG;
+  if (P->cellgeo != 0 && (P->cellgeo != 1 || P->op != 0)) return ORC_ERR_ARG;
   int n = P->degree + 1, n2 = n * n, n3 = n2 * n;
   c->n = n;
   c->n3 = n3;
@@ -388,6 +401,29 @@ static void geom_at(const orc_ctx *c, const int ci[3], const double xi[3], doubl
   }
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) J[i][j] = G[i][j] * c->h[j];
+}
+
+/* Point x and Jacobian at Gauss point q of cell ci of the interpolant of the
+ * map through the cell's n^3 Gauss points: dx_i/dxi_d = sum_m x_i(point q with
+ * its index along d replaced by m) l_m'(g_{q_d}), l_m the Lagrange
+ * polynomials on the n Gauss points. */
+static void geom_interp_at(const orc_ctx *c, const int ci[3], int q, double x[3], double J[3][3])
+{
+  const int n = c->n;
+  const int qi[3] = {q % n, (q / n) % n, q / (n * n)};
+  const double xi[3] = {c->gx[qi[0]], c->gx[qi[1]], c->gx[qi[2]]};
+  double Jmap[3][3];
+  geom_at(c, ci, xi, x, Jmap);
+  for (int d = 0; d < 3; ++d) {
+    for (int i = 0; i < 3; ++i) J[i][d] = 0.0;
+    for (int m = 0; m < n; ++m) {
+      double xm_ref[3] = {xi[0], xi[1], xi[2]}, xm[3], Jm[3][3];
+      xm_ref[d] = c->gx[m];
+      geom_at(c, ci, xm_ref, xm, Jm);
+      const double dl = lag_der(n, c->gx, m, xi[d]);
+      for (int i = 0; i < 3; ++i) J[i][d] += xm[i] * dl;
+    }
+  }
 }
 
 /* Inverse by the adjugate; returns det. */
@@ -480,7 +516,8 @@ static int local_apply(const orc_ctx *c, int64_t e, const double *u_own,
     double xi[3] = {c->gx[q % n], c->gx[(q / n) % n], c->gx[q / n2]};
     double W = c->gw[q % n] * c->gw[(q / n) % n] * c->gw[q / n2];
     double x[3], J[3][3], Ji[3][3];
-    geom_at(c, ci, xi, x, J);
+    if (c->P.cellgeo == 1) geom_interp_at(c, ci, q, x, J);
+    else geom_at(c, ci, xi, x, J);
     double det = inv3(J, Ji);
     if (!(det > 0.0)) return ORC_ERR_GEOM;
     double gref[3] = {0.0, 0.0, 0.0}, gu[3];
@@ -801,6 +838,36 @@ int orc_block_rows(const orc_problem *P, const int64_t *cells, int64_t ncells, d
  * (area element times weight), out[7..9] x from the neighbour side, out[10]
  * ds from the neighbour side (both zero at the boundary), out[11] = 1 if
  * interior. */
+/* The cell Jacobian the SIPG cell term uses at Gauss point q of cell e
+ * (J[3*i + d] = dx_i/dxi_d; the interpolant's for cellgeo = 1) and the map's
+ * own (Jmap, same layout). */
+int orc_cell_jacobian(const orc_problem *P, int64_t e, int q, double *J, double *Jmap)
+{
+  orc_ctx c;
+  int rc = ctx_init(&c, P);
+  if (rc) return rc;
+  const int64_t total = (int64_t)P->ncell[0] * P->ncell[1] * P->ncell[2];
+  if (e < 0 || e >= total || q < 0 || q >= c.n3) {
+    ctx_free(&c);
+    return ORC_ERR_ARG;
+  }
+  int ci[3];
+  cell_coords(&c, e, ci);
+  const int n = c.n;
+  const double xi[3] = {c.gx[q % n], c.gx[(q / n) % n], c.gx[q / (n * n)]};
+  double x[3], Ja[3][3], Jb[3][3];
+  geom_at(&c, ci, xi, x, Ja);
+  if (P->cellgeo == 1) geom_interp_at(&c, ci, q, x, Jb);
+  else memcpy(Jb, Ja, sizeof(Ja));
+  for (int i = 0; i < 3; ++i)
+    for (int d = 0; d < 3; ++d) {
+      J[3 * i + d] = Jb[i][d];
+      Jmap[3 * i + d] = Ja[i][d];
+    }
+  ctx_free(&c);
+  return ORC_OK;
+}
+
 int orc_face_point(const orc_problem *P, int64_t e, int f, int q1, int q2, double *out)
 {
   orc_ctx c;
