@@ -33,7 +33,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1711_03590_amd", "csrc", "kernels.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sipg_apply_f64_curved_k4_32cubed_traffic.txt")
 
 
-GEOMETRY_VALUES = {"curved": (10, 4), "curved-merged": (6, 4), "affine-variable": (1, 1), "affine": (0, 0),
+GEOMETRY_VALUES = {"curved": (10, 4), "curved-merged": (6, 4), "curved-positions": (4, 4), "affine-variable": (1, 1), "affine": (0, 0),
                    "advection": (3, 1)}
 
 
@@ -43,7 +43,9 @@ def algorithmic_bytes_per_dof(ncell, k, real_bytes, geometry="curved"):
     quadrature point (n.J^{-1}, c ds); affine with a variable coefficient:
     c det J w per cell point and c ds per face point; affine with a constant
     coefficient: nothing.  Merged curved storage (G4): the 6 entries of the
-    symmetric c det J w J^{-1} J^{-T} per cell point, faces as G3.  The
+    symmetric c det J w J^{-1} J^{-T} per cell point, faces as G3.  Positions
+    storage (G2): the 3 position components and c per cell point, faces as
+    G3.  The
     advection operator: J^{-1} c det J w per cell point and (c.n) ds per face
     point.  Neighbour re-reads and tables are not counted."""
     n = k + 1
@@ -207,9 +209,10 @@ def main():
 
     del flush
     hbm = measure_hbm(torch)
-    variants = merged = advection = hermite = degrees = None
+    variants = merged = positions = advection = hermite = degrees = None
     if args.variants:
         merged = bench_merged(dg, torch, synth, N, k, args.steps, args.warmup, res)
+        positions = bench_merged(dg, torch, synth, N, k, args.steps, args.warmup, res, storage="positions")
         hermite = bench_hermite(dg, torch, synth, N, k, args.steps, args.warmup, res)
         advection = bench_advection(dg, torch, synth, N, k, args.steps, args.warmup)
         variants = bench_variants(dg, torch, synth, k)
@@ -267,6 +270,8 @@ def main():
                         "per_launch_us": r["per_launch_us"], "speedup_vs_fp64": r["dofs"] / head["dofs"]}
     if merged:
         line["merged_geometry"] = merged
+    if positions:
+        line["positions_geometry"] = positions
     if hermite:
         line["hermite_basis"] = hermite
     if advection:
@@ -340,19 +345,23 @@ def bench_degrees(dg, torch, synth, ncell=32, degrees=range(2, 9), steps=50):
     return out
 
 
-def bench_merged(dg, torch, synth, ncell, k, steps, warmup, g3):
+def bench_merged(dg, torch, synth, ncell, k, steps, warmup, g3, storage="merged"):
     """The headline workload with the merged cell geometry (G4): same
-    operator up to rounding, 6 instead of 10 values per cell point."""
-    op = dg.Operator(ncell, k, curved=True, amplitude=synth.AMPLITUDE, merged=True)
+    operator up to rounding, 6 instead of 10 values per cell point; or
+    (storage="positions") with the quadrature-point positions (G2): 4 values
+    per point, Jacobians by collocation derivatives in the kernel."""
+    op = dg.Operator(ncell, k, curved=True, amplitude=synth.AMPLITUDE, storage=storage)
     nd = op.n_dofs
     src = synth.src_vector(nd, synth.seed_for(2, k))
-    out = {"workload": f"{ncell}^3 sine-curved, k={k}, merged cell geometry (G4)"}
+    name = "curved-merged" if storage == "merged" else "curved-positions"
+    label = "merged cell geometry (G4)" if storage == "merged" else "cell geometry from quadrature-point positions (G2)"
+    out = {"workload": f"{ncell}^3 sine-curved, k={k}, {label}"}
     for prec in ("f64", "f32"):
         dt = torch.float64 if prec == "f64" else torch.float32
         x = torch.from_numpy(src).to(dtype=dt, device="cuda")
         y = torch.empty_like(x)
         ms = time_apply(op, x, y, steps, warmup, torch)
-        bpd = algorithmic_bytes_per_dof(ncell, k, 8 if prec == "f64" else 4, "curved-merged")
+        bpd = algorithmic_bytes_per_dof(ncell, k, 8 if prec == "f64" else 4, name)
         gbs = bpd * nd / (ms * 1e-3) / 1e9
         out[prec] = {"dofs_per_s": nd / (ms * 1e-3), "us": ms * 1e3, "algorithmic_bytes_per_dof": bpd,
                      "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}

@@ -80,9 +80,17 @@ typedef enum { DG_MAP_AFFINE = 0, DG_MAP_SINE = 1 } dg_map;
  *                    applies (the residuals of mixed-precision refinement)
  *                    see the stored Jacobians, FP32 applies (the inner
  *                    solver) the cheaper merged coefficient.
- * All give the same operator up to rounding; faces store j = J^{-1} n and
- * c ds either way.  Ignored for DG_MAP_AFFINE. */
-typedef enum { DG_STORE_JACOBIAN = 0, DG_STORE_MERGED = 1, DG_STORE_MIXED = 2 } dg_storage;
+ * These give the same operator up to rounding.
+ * DG_STORE_POSITIONS the physical quadrature-point positions (relative to
+ *                    the cell's unmapped corner) and c, 4 values (G2): the
+ *                    kernel takes the cell Jacobian as the collocation
+ *                    derivative of the positions, i.e. the Jacobian of the
+ *                    degree-k interpolant of the map through the Gauss points.
+ *                    A slightly different operator (equal on affine maps,
+ *                    converging to the others at order k in the Jacobian).
+ * Faces store j = J^{-1} n and c ds in every case.  Ignored for
+ * DG_MAP_AFFINE. */
+typedef enum { DG_STORE_JACOBIAN = 0, DG_STORE_MERGED = 1, DG_STORE_MIXED = 2, DG_STORE_POSITIONS = 3 } dg_storage;
 typedef struct {
   dg_map map;
   double amplitude;

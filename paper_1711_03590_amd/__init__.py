@@ -18,17 +18,19 @@ DG_OK, DG_ERR_ARG, DG_ERR_OOM, DG_ERR_HIP, DG_ERR_UNSUPPORTED, DG_ERR_NOT_CONVER
 F64, F32 = 0, 1
 DIRICHLET, NEUMANN = 0, 1
 MAP_AFFINE, MAP_SINE = 0, 1
-STORE_JACOBIAN, STORE_MERGED, STORE_MIXED = 0, 1, 2
+STORE_JACOBIAN, STORE_MERGED, STORE_MIXED, STORE_POSITIONS = 0, 1, 2, 3
 
 
 def _storage(merged, storage):
-    """storage "jacobian" (G3), "merged" (G4) or "mixed" (G3 in FP64, G4 in
-    FP32); merged=True is short for "merged"."""
+    """storage "jacobian" (G3), "merged" (G4), "mixed" (G3 in FP64, G4 in
+    FP32) or "positions" (G2: quadrature-point positions, Jacobians taken in
+    the kernel); merged=True is short for "merged"."""
     if storage is None:
         storage = "merged" if merged else "jacobian"
-    table = {"jacobian": STORE_JACOBIAN, "merged": STORE_MERGED, "mixed": STORE_MIXED}
+    table = {"jacobian": STORE_JACOBIAN, "merged": STORE_MERGED, "mixed": STORE_MIXED,
+             "positions": STORE_POSITIONS}
     if storage not in table:
-        raise ValueError("storage must be 'jacobian', 'merged' or 'mixed'")
+        raise ValueError("storage must be 'jacobian', 'merged', 'mixed' or 'positions'")
     return table[storage]
 COEF_CONST, COEF_SINCOS = 0, 1
 PREC_F64, PREC_F32 = 1, 2

@@ -79,6 +79,7 @@ __device__ __noinline__ void batch_apply_one(const BatchSlot &sl, int blk, float
   switch (sl.gk) {
     case CURVED: apply_batch<N, float, CURVED, kBatchTpb>(sl.v, sl.p, sl.q, blk, smem); break;
     case CURVED_MERGED: apply_batch<N, float, CURVED_MERGED, kBatchTpb>(sl.v, sl.p, sl.q, blk, smem); break;
+    case CURVED_POS: apply_batch<N, float, CURVED_POS, kBatchTpb>(sl.v, sl.p, sl.q, blk, smem); break;
     case AFFINE_VAR: apply_batch<N, float, AFFINE_VAR, kBatchTpb>(sl.v, sl.p, sl.q, blk, smem); break;
     default: apply_batch<N, float, AFFINE_CONST, kBatchTpb>(sl.v, sl.p, sl.q, blk, smem); break;
   }

@@ -20,14 +20,19 @@ namespace dgk {
 //                 point; faces as CURVED
 //   ADVECTION     the advection operator (Sec. 2, Eq. (1)): J^{-1} c det J w
 //                 (3) per cell point, (c . n) ds for the +e_a normal per face point
-enum GeomKind : int { AFFINE_CONST = 0, AFFINE_VAR = 1, CURVED = 2, CURVED_MERGED = 3, ADVECTION = 4 };
+//   CURVED_POS    G2: the quadrature-point positions (3, relative to the
+//                 cell's unmapped corner) and c per cell point, the Jacobian
+//                 taken in the kernel by collocation derivatives; faces as CURVED
+enum GeomKind : int { AFFINE_CONST = 0, AFFINE_VAR = 1, CURVED = 2, CURVED_MERGED = 3, ADVECTION = 4, CURVED_POS = 5 };
 
 // faces carry j = J^{-1} n and c ds per point
-constexpr bool curved_faces(int gk) { return gk == CURVED || gk == CURVED_MERGED; }
+constexpr bool curved_faces(int gk) { return gk == CURVED || gk == CURVED_MERGED || gk == CURVED_POS; }
 // stored values per cell quadrature point
 constexpr int cell_values(int gk)
 {
-  return gk == CURVED ? 10 : (gk == CURVED_MERGED ? 6 : (gk == ADVECTION ? 3 : (gk == AFFINE_VAR ? 1 : 0)));
+  return gk == CURVED ? 10
+                      : (gk == CURVED_MERGED ? 6
+                                             : (gk == CURVED_POS ? 4 : (gk == ADVECTION ? 3 : (gk == AFFINE_VAR ? 1 : 0))));
 }
 constexpr int face_values(int gk) { return curved_faces(gk) ? 4 : ((gk == AFFINE_VAR || gk == ADVECTION) ? 1 : 0); }
 
@@ -42,7 +47,8 @@ constexpr int kMaxN = 9;  // degree 8
 template <typename Real>
 struct GeomData {
   const Real *cell = nullptr;          // CURVED: 10 arrays (J^{-T} row-major, then cJxW);
-                                       // CURVED_MERGED: 6 (M00, M01, M02, M11, M12, M22); AFFINE_VAR: 1 (cJxW)
+                                       // CURVED_MERGED: 6 (M00, M01, M02, M11, M12, M22);
+                                       // CURVED_POS: 4 (x - X0, y - Y0, z - Z0, c); AFFINE_VAR: 1 (cJxW)
   const Real *face[3] = {nullptr, nullptr, nullptr};  // curved: 4 arrays (j0, j1, j2, cds); AFFINE_VAR: 1 (cds)
   int64_t cell_stride = 0;             // elements between successive quantity arrays
   int64_t face_stride[3] = {0, 0, 0};

@@ -251,6 +251,17 @@ __global__ void geom_cells_kernel(const GeoArgs g, int64_t npts, double *o64, fl
       if (o64) o64[b * stride + idx] = t;
       if (o32) o32[b * stride + idx] = (float)t;
     }
+  } else if (GK == CURVED_POS) {
+    // the point relative to the cell's unmapped corner (small numbers, so
+    // that FP32 keeps the differences the collocation derivative takes), and c
+    for (int d = 0; d < 3; ++d) {
+      const double v = x[d] - (g.lo[d] + ci[d] * g.h[d]);
+      if (o64) o64[d * stride + idx] = v;
+      if (o32) o32[d * stride + idx] = (float)v;
+    }
+    const double c = coef_value(g, x);
+    if (o64) o64[3 * stride + idx] = c;
+    if (o32) o32[3 * stride + idx] = (float)c;
   } else if (GK == CURVED_MERGED) {
     // M = c det J w J^{-1} J^{-T}: M[b][c] = cjxw sum_a J^{-T}[a][b] J^{-T}[a][c]
     double jt[3][3];
@@ -495,6 +506,7 @@ static int64_t geom_face_values(int gk) { return face_values(gk); }
 static int geom_kind(const dg_geometry *geom, const dg_coefficient *coef, bool f32 = false)
 {
   if (geom->map == DG_MAP_SINE) {
+    if (geom->storage == DG_STORE_POSITIONS) return CURVED_POS;
     if (geom->storage == DG_STORE_MERGED || (f32 && geom->storage == DG_STORE_MIXED)) return CURVED_MERGED;
     return CURVED;
   }
@@ -534,7 +546,8 @@ static dg_status validate(const dg_mesh *mesh, int degree, const dg_geometry *ge
   for (int f = 0; f < 6; ++f)
     if (mesh->bc[f] != DG_BC_DIRICHLET && mesh->bc[f] != DG_BC_NEUMANN) return fail(DG_ERR_ARG, "bad bc");
   if (geom->map != DG_MAP_AFFINE && geom->map != DG_MAP_SINE) return fail(DG_ERR_ARG, "bad map");
-  if (geom->storage != DG_STORE_JACOBIAN && geom->storage != DG_STORE_MERGED && geom->storage != DG_STORE_MIXED)
+  if (geom->storage != DG_STORE_JACOBIAN && geom->storage != DG_STORE_MERGED && geom->storage != DG_STORE_MIXED &&
+      geom->storage != DG_STORE_POSITIONS)
     return fail(DG_ERR_ARG, "bad geometry storage");
   if (coef->kind != DG_COEF_CONST && coef->kind != DG_COEF_SINCOS) return fail(DG_ERR_ARG, "bad coefficient");
   if (precisions == 0 || (precisions & ~3u)) return fail(DG_ERR_ARG, "precisions must be a nonempty subset of F64|F32");
@@ -745,6 +758,8 @@ static dg_status setup_impl(const dg_mesh *mesh, int degree, int basis, const dg
       if (gk == CURVED) hipLaunchKernelGGL(geom_cells_kernel<CURVED>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
       else if (gk == CURVED_MERGED)
         hipLaunchKernelGGL(geom_cells_kernel<CURVED_MERGED>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
+      else if (gk == CURVED_POS)
+        hipLaunchKernelGGL(geom_cells_kernel<CURVED_POS>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
       else if (gk == ADVECTION)
         hipLaunchKernelGGL(geom_cells_kernel<ADVECTION>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
       else if (gk == AFFINE_VAR)

@@ -714,6 +714,28 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
     __syncthreads();
     if (act) {
       Real qz[N], dz[N], t2v[N];
+      // G2: the Dco rows of this thread's x and y indices, and its two weights
+      Real d1[N], d2[N], w12 = Real(0);
+      if constexpr (GK == CURVED_POS) {
+        const int i1 = l % N, i2 = l / N;
+        Real w1 = Real(0), w2 = Real(0);
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          if (q == i1) w1 = Real(T.gw[q]);
+          if (q == i2) w2 = Real(T.gw[q]);
+        }
+        w12 = w1 * w2;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          d1[j] = Real(0);
+          d2[j] = Real(0);
+#pragma unroll
+          for (int q = 0; q < N; ++q) {
+            if (q == i1) d1[j] = Real(T.Dco[q][j]);
+            if (q == i2) d2[j] = Real(T.Dco[q][j]);
+          }
+        }
+      }
       load_line<N, 2>(Q, l, qz);
       eo_apply<N, M_DCO>(qz, dz);
 #pragma unroll
@@ -739,6 +761,47 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
           o[2] = M[2] * g[0] + M[4] * g[1] + M[5] * g[2];
           __builtin_amdgcn_sched_barrier(0);
           if (k + NB < N) load_geometry(k + NB, gbuf[k % NB]);
+        } else if constexpr (GK == CURVED_POS) {
+          // G2 (Sec. 5): columns a_d = dx/dxi_d of the Jacobian by collocation
+          // derivatives of the stored positions along the x, y and z lines
+          // through this point (L1-resident: the cell's positions are read
+          // by all its threads); with C_d = a_{d+1} x a_{d+2} and
+          // det = a_0 . C_0, J^{-T} g = sum_d C_d g_d / det and
+          // t_e = c w / det * C_e . (sum_d C_d g_d)
+          const Real *P = op.g.cell + (int64_t)cell * N3;
+          const int64_t cs = op.g.cell_stride;
+          const int i1 = l % N, i2 = l / N;
+          Real a[3][3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            // one component at a time, so that at most 3N loads are in flight
+            __builtin_amdgcn_sched_barrier(0);
+            Real sx = Real(-0.0), sy = Real(-0.0), sz = Real(-0.0);
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+              sx = fma(d1[j], P[c * cs + j + N * i2 + N2 * k], sx);
+              sy = fma(d2[j], P[c * cs + i1 + N * j + N2 * k], sy);
+              sz = madd(T.Dco[k][j], P[c * cs + l + N2 * j], sz);
+            }
+            a[0][c] = sx;
+            a[1][c] = sy;
+            a[2][c] = sz;
+          }
+          Real C[3][3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const Real *u = a[(d + 1) % 3], *v = a[(d + 2) % 3];
+            C[d][0] = u[1] * v[2] - u[2] * v[1];
+            C[d][1] = u[2] * v[0] - u[0] * v[2];
+            C[d][2] = u[0] * v[1] - u[1] * v[0];
+          }
+          const Real det = a[0][0] * C[0][0] + a[0][1] * C[0][1] + a[0][2] * C[0][2];
+          const Real cw = P[3 * cs + p] * w12 * Real(T.gw[k]) / det;
+          Real v[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) v[c] = C[0][c] * g[0] + C[1][c] * g[1] + C[2][c] * g[2];
+#pragma unroll
+          for (int e = 0; e < 3; ++e) o[e] = cw * (C[e][0] * v[0] + C[e][1] * v[1] + C[e][2] * v[2]);
         }
         G0[p] = o[0];
         G1[p] = o[1];
@@ -842,6 +905,7 @@ sipg_diag_kernel(const OpView<double> op, double *__restrict__ d64, float *__res
   constexpr BasisTables<N> BT = kBasis<N, BS>;
   __shared__ double Sl[N2], Dl[N2];      // S[q][j], D[q][j] (basis function j at Gauss point q)
   __shared__ double Fe[2 * N];           // D_f end rows: F0[j], F1[j]
+  __shared__ double Dcl[N2];             // Dco[q][m] (positions storage)
   __shared__ double M[6 * N3];           // M00 M01 M02 M11 M12 M22 per point
   __shared__ double T1[N3], T2[N3];
   const int cell = blockIdx.x;
@@ -857,8 +921,11 @@ sipg_diag_kernel(const OpView<double> op, double *__restrict__ d64, float *__res
       }
       Fe[q] = BT.F0[q];
       Fe[N + q] = BT.F1[q];
+#pragma unroll
+      for (int m = 0; m < N; ++m) Dcl[q * N + m] = T.Dco[q][m];
     }
   }
+  if constexpr (GK == CURVED_POS) __syncthreads();  // Dcl is read below
   // effective coefficient at quadrature point q = i
   if (act) {
     const int64_t ix = (int64_t)cell * N3 + i;
@@ -876,6 +943,35 @@ sipg_diag_kernel(const OpView<double> op, double *__restrict__ d64, float *__res
     } else if constexpr (GK == CURVED_MERGED) {
 #pragma unroll
       for (int e = 0; e < 6; ++e) m[e] = op.g.cell[e * cs + ix];
+    } else if constexpr (GK == CURVED_POS) {
+      // the Jacobian's columns by collocation derivatives of the positions,
+      // then M = c w det J^{-1} J^{-T} = c w / det C^T C (C_d = a_{d+1} x a_{d+2})
+      const int qi[3] = {i % N, (i / N) % N, i / N2};
+      const int64_t c0 = (int64_t)cell * N3;
+      double a[3][3];
+      for (int d = 0; d < 3; ++d)
+        for (int c = 0; c < 3; ++c) {
+          double sum = 0.0;
+          for (int mm = 0; mm < N; ++mm) {
+            int r[3] = {qi[0], qi[1], qi[2]};
+            r[d] = mm;
+            sum += Dcl[qi[d] * N + mm] * op.g.cell[c * cs + c0 + r[0] + N * r[1] + N2 * r[2]];
+          }
+          a[d][c] = sum;
+        }
+      double C[3][3];
+      for (int d = 0; d < 3; ++d) {
+        const double *u = a[(d + 1) % 3], *v = a[(d + 2) % 3];
+        C[d][0] = u[1] * v[2] - u[2] * v[1];
+        C[d][1] = u[2] * v[0] - u[0] * v[2];
+        C[d][2] = u[0] * v[1] - u[1] * v[0];
+      }
+      const double det = a[0][0] * C[0][0] + a[0][1] * C[0][1] + a[0][2] * C[0][2];
+      const double f = op.g.cell[3 * cs + ix] * T.gw[qi[0]] * T.gw[qi[1]] * T.gw[qi[2]] / det;
+      const int rb[6] = {0, 0, 0, 1, 1, 2}, rc[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+      for (int e = 0; e < 6; ++e)
+        m[e] = f * (C[rb[e]][0] * C[rc[e]][0] + C[rb[e]][1] * C[rc[e]][1] + C[rb[e]][2] * C[rc[e]][2]);
     } else {
       double f;
       if constexpr (GK == AFFINE_VAR) f = op.g.cell[ix];
@@ -992,6 +1088,7 @@ __host__ void sipg_variant(const dg_op *op, bool f32, F &&f)
     switch (f32 ? op->gk32 : op->gk) {
       case CURVED: f(std::integral_constant<int, CURVED>{}, bs); break;
       case CURVED_MERGED: f(std::integral_constant<int, CURVED_MERGED>{}, bs); break;
+      case CURVED_POS: f(std::integral_constant<int, CURVED_POS>{}, bs); break;
       case AFFINE_VAR: f(std::integral_constant<int, AFFINE_VAR>{}, bs); break;
       default: f(std::integral_constant<int, AFFINE_CONST>{}, bs); break;
     }

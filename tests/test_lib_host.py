@@ -190,3 +190,13 @@ def test_footprint_mixed_storage(dg):
     assert dg.footprint(N, k, curved=True, storage="mixed", precisions=dg.PREC_F32) == f32
     with pytest.raises(ValueError):
         dg.footprint(N, k, curved=True, storage="packed")
+
+
+def test_footprint_positions_storage(dg):
+    # 3 positions and c per cell point, faces as G3, the diagonal
+    k, N = 4, 32
+    n = k + 1
+    cells = N ** 3
+    faces = 3 * N * N * (N + 1)
+    vals = 4 * cells * n ** 3 + 4 * faces * n ** 2 + cells * n ** 3
+    assert dg.footprint(N, k, curved=True, storage="positions") == vals * 12
