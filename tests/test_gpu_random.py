@@ -28,7 +28,7 @@ def _case(seed):
               bc=tuple(int(v) for v in rng.integers(0, 2, size=6)), lo=lo, hi=hi)
     if not kw["variable_coef"]:
         kw["coef_value"] = float(rng.uniform(0.5, 3.0))
-    storage = ["jacobian", "merged", "mixed"][int(rng.integers(0, 3))]
+    storage = ["jacobian", "merged", "mixed", "positions"][int(rng.integers(0, 4))]
     basis = "hermite" if k >= 3 and rng.integers(0, 2) else "nodal"
     return ncell, k, kw, storage, basis
 
@@ -52,7 +52,8 @@ def test_random_configuration(dg, orc, seed):
     ncell, k, kw, storage, basis = _case(seed)
     print(f"random case {seed}: ncell={ncell} k={k} {kw} storage={storage} basis={basis}", flush=True)
     op = dg.Operator(ncell, k, storage=storage, basis=basis, **kw)
-    p = orc.problem(ncell, k, basis="hermite" if basis == "hermite" else "gll", **kw)
+    geo = "positions" if storage == "positions" and kw["curved"] else "map"
+    p = orc.problem(ncell, k, basis="hermite" if basis == "hermite" else "gll", cell_geometry=geo, **kw)
     src = synth.src_vector(op.n_dofs, 500 + seed)
     ref = orc.apply(p, src)
     dst = torch.full((op.n_dofs,), float("nan"), dtype=torch.float64, device="cuda")
