@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -65,6 +66,7 @@ struct OpView {
   Real c_vol;               // AFFINE_CONST: c * hx * hy * hz
   Real c_area[3];           // AFFINE_CONST: c * h_t1 * h_t2 for faces normal to a
   GeomData<Real> g;
+  int reverse = 0;          // walk the cell batches last to first (set per launch)
 };
 
 }  // namespace dgk
@@ -77,6 +79,7 @@ struct dg_op {
   dg_coefficient coef;
   dg_velocity vel{};         // advection ops only
   int basis = 0;             // SIPG ops: DG_BASIS_NODAL or DG_BASIS_HERMITE
+  mutable std::atomic<unsigned> sweeps{0};  // SIPG applies so far: odd ones walk the cells backwards
   unsigned precisions = 0;
   int gk = 0;                // geometry kind of the FP64 data (and of the op)
   int gk32 = 0;              // geometry kind of the FP32 data (differs for DG_STORE_MIXED)

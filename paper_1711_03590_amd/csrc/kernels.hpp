@@ -876,7 +876,11 @@ sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__r
 {
   using BK = Blocking<N>;
   __shared__ Real smem[BK::SMEM];
-  apply_batch<N, Real, GK, BK::TPB, DOT, BS>(op, src, dst, xcd_remap(blockIdx.x, gridDim.x), smem, dot);
+  // successive applies walk the cells in opposite orders, so that each
+  // starts on the data the previous one touched last (still in the MALL
+  // when the operand set exceeds it); the result does not depend on it
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  apply_batch<N, Real, GK, BK::TPB, DOT, BS>(op, src, dst, op.reverse ? (int)gridDim.x - 1 - b : b, smem, dot);
 }
 
 // ---------------------------------------------------------------------------
@@ -1116,9 +1120,11 @@ hipError_t launch_apply(const dg_op *op, const void *src, void *dst, bool f32, h
       hipLaunchKernelGGL((adv_apply_kernel<N, Real>), dim3(grid), dim3(BK::TPB), 0, s, view, x, y);
       return;
     }
+    auto v = view;
+    v.reverse = (int)(op->sweeps.fetch_add(1, std::memory_order_relaxed) & 1u);
     sipg_variant<N>(op, f32, [&](auto gk, auto bs) {
       hipLaunchKernelGGL((sipg_apply_kernel<N, Real, decltype(gk)::value, false, decltype(bs)::value>), dim3(grid),
-                         dim3(BK::TPB), 0, s, view, x, y, DotOut<Real>{});
+                         dim3(BK::TPB), 0, s, v, x, y, DotOut<Real>{});
     });
   };
   if (f32) go(0.0f, op->v32);
@@ -1139,9 +1145,11 @@ hipError_t launch_apply_dot(const dg_op *op, const void *src, void *dst, bool f3
     const Real *x = static_cast<const Real *>(src);
     Real *y = static_cast<Real *>(dst);
     DotOut<Real> d{static_cast<Real *>(part)};
+    auto v = view;
+    v.reverse = (int)(op->sweeps.fetch_add(1, std::memory_order_relaxed) & 1u);
     sipg_variant<N>(op, f32, [&](auto gk, auto bs) {
       hipLaunchKernelGGL((sipg_apply_kernel<N, Real, decltype(gk)::value, true, decltype(bs)::value>), dim3(grid),
-                         dim3(BK::TPB), 0, s, view, x, y, d);
+                         dim3(BK::TPB), 0, s, v, x, y, d);
     });
   };
   if (f32) go(0.0f, op->v32);

@@ -218,3 +218,15 @@ def test_apply_largest_size(dg, orc):
     del x, src
     op.close()
     torch.cuda.empty_cache()
+
+
+def test_alternating_sweep_order_is_invisible(dg):
+    """Successive applies walk the cells in opposite orders (MALL reuse);
+    every apply still returns bitwise the same result."""
+    import torch
+    for kw in (dict(curved=True), dict(curved=True, merged=True), dict(variable_coef=True)):
+        op = dg.Operator((9, 7, 6), 4, **kw)
+        u = torch.from_numpy(synth.src_vector(op.n_dofs, 77)).cuda()
+        ys = [op.apply(u) for _ in range(3)]
+        assert torch.equal(ys[0], ys[1]) and torch.equal(ys[1], ys[2])
+        op.close()
