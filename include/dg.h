@@ -201,8 +201,8 @@ int64_t dg_n_dofs(const dg_op *op);
 
 /* dst := A src (Sec. 2, Eq. (3)) for the op's operator (SIPG Laplacian or
  * advection), one fused pass over all cells: each cell computes its cell
- * integral and the own-side share of its six face integrals (Algorithm 1,
- * steps (ii)-(iv)) and writes its dst block once; dst need not be
+ * integral and the own-side share of its six face integrals (the cell and
+ * face loops of Algorithm 1, fused) and writes its dst block once; dst need not be
  * initialised.  src and dst must have the same dtype, which must be enabled in
  * the op, length dg_n_dofs, and must not alias: otherwise DG_ERR_ARG and nothing
  * is enqueued. */

@@ -19,8 +19,9 @@
 //       instead of a block), then the 2D basis change S x S; upwind flux with
 //       the stored (c.n) ds; integration onto the own normal line with the
 //       end values;
-//   (d) quadrature-point operation t = (J^{-1} c det J w) u (Algorithm 1
-//       step (c)) and the transposed collocation derivatives, subtracted from
+//   (d) quadrature-point operation t = (J^{-1} c det J w) u (the
+//       quadrature-point work of Algorithm 1) and the transposed collocation
+//       derivatives, subtracted from
 //       the residual;
 //   (e) S^T x S^T x S^T and one coalesced write.
 // Boundary faces: u+ = -u- (mirror, homogeneous inflow data) on bc 0 faces,

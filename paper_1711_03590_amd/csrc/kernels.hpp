@@ -6,7 +6,8 @@
 // evaluated cell by cell, in the nodal Gauss-Lobatto basis or the
 // Hermite-like basis (template parameter BS, see tables.hpp).  Each workgroup owns B = TPB / N^2 cells and maps
 // one thread to one 1D line of each cell (N^2 lines per sweep direction).
-// Per cell, in one pass (Algorithm 1 steps (ii)-(iv) fused, Design Choice 2):
+// Per cell, in one pass (the cell and face loops of Algorithm 1 fused,
+// Design Choice 2):
 //   (a) gather the cell's N^3 coefficients into LDS (coalesced block copy);
 //   (b) basis change to the Gauss points, S x S x S (Sec. 2, Eq. (6)), every
 //       1D matvec done with the even-odd decomposition (Sec. 3.3, Eq. (8));
@@ -21,7 +22,7 @@
 //       gradient; numerical flux of Eq. (2) with the stored
 //       normal-times-inverse-Jacobian j (Design Choice 5); own-side
 //       integration back onto the quadrature-point residual;
-//   (d) cell quadrature-point operation (Algorithm 1 step (c)): collocation
+//   (d) cell quadrature-point operation (that of Algorithm 1): collocation
 //       derivatives Dco along x, y, z, t = J^{-1} (c det J w) J^{-T} grad_xi u,
 //       then the transposed derivatives sum the three components into the
 //       residual;
@@ -348,7 +349,7 @@ __device__ __forceinline__ void for_jobs(int l, bool act, F &&f)
 
 // Face terms of direction A for this thread group's cell: the face integrals
 // of Sec. 2 Eq. (2) over the cell's two faces normal to A, own side only
-// (the element's share of Algorithm 1 steps (iii)-(iv)), added into the
+// (the element's share of Algorithm 1's face loops), added into the
 // quadrature-point residual R along the normal lines.  Q holds the cell's
 // values at the Gauss points; W is 10 N^2 of scratch.
 //   [[u]] = u- - u+, {{grad u}} = (grad u- + grad u+)/2; the average's
@@ -465,7 +466,7 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
     });
     __syncthreads();
   }
-  // S6: numerical flux at this face point (Algorithm 1 step (c) for faces)
+  // S6: numerical flux at this face point (Algorithm 1's quadrature-point work on faces)
   Real tv[2] = {Real(0), Real(0)}, tga[2] = {Real(0), Real(0)};
   if (act) {
 #pragma unroll
