@@ -146,7 +146,35 @@ def cpu_baseline(ncell, k, budget_s=12.0):
             break
     return {"value": done * n3 / el, "unit": "DoF/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{len(cells)} cells ({len(cells) * n3} DoFs) of the 32^3 curved k=4 mesh, "
-                      f"applied {done // len(cells)} times in {el:.1f} s"}
+                      f"applied {done // len(cells)} times in {el:.1f} s",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+FLOP_PER_DOF_F64_K4 = 235.0     # SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes per DoF, curved k=4 apply (rocprofv3)
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+# The paper's own figures for its 3D SIPG Laplacian, on Intel CPUs with a
+# Hermite-like basis (FP64 unless stated): context only, not a target.
+PAPER_CONTEXT = {
+    "note": "Intel CPU results of the paper (Hermite-like basis, Cartesian meshes); context, not comparable one to one",
+    "broadwell_2x14_full_operator_dofs_per_s": {"p2": 1.243e9, "p3": 1.336e9, "p5": 1.527e9, "p8": 1.203e9},
+    "broadwell_or_knl_operator_without_exchange_dofs_per_s": "1.8e9 to 2.1e9 for 3 <= p <= 8",
+    "knl_64_cores_compute_only_dofs_per_s": "above 3e9 for 2 <= p <= 10",
+    "haswell_e5_2697v3_node_p5_56.6M_dofs": {"fp64_dofs_per_s": 1.36e9, "fp32_dofs_per_s": 2.59e9},
+    "hypershell_geometry_computed_on_the_fly_dofs_per_s": "at most 3.5e8 (28 Broadwell cores)",
+}
 
 
 def main():
@@ -262,6 +290,12 @@ def main():
                      "kernel": f"sipg_apply_kernel<{k + 1}, {'double' if headp == 'f64' else 'float'}, CURVED>"},
     }
     line["per_launch_us"] = head["per_launch_us"]
+    if headp == "f64" and k == 4:
+        # FP64 operations per DoF of this kernel from SQ_INSTS_VALU_*_F64
+        # counters (FMA = 2), against the FP64 vector peak
+        line["flop_rate"] = {"flop_per_dof": FLOP_PER_DOF_F64_K4, "tflops": head["dofs"] * FLOP_PER_DOF_F64_K4 / 1e12,
+                             "peak_tflops": FP64_VECTOR_PEAK_TFLOPS,
+                             "frac": head["dofs"] * FLOP_PER_DOF_F64_K4 / 1e12 / FP64_VECTOR_PEAK_TFLOPS}
     line["hbm_measured"] = dict(hbm, frac_of_read=head["achieved_gbs"] / hbm["read_gbs"])
     if "f32" in res and headp == "f64":
         r = res["f32"]
@@ -286,6 +320,7 @@ def main():
         line["serve"] = serving
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(N, k)
+    line["paper_context"] = PAPER_CONTEXT
     print(json.dumps(line), flush=True)
     op.close()
 
