@@ -286,6 +286,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": head["frac"],
                      "traffic": head["traffic"],
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes_per_launch": head["bytes_per_dof"] * nd,
                      "algorithmic_bytes_per_dof": head["bytes_per_dof"],
                      "kernel": f"sipg_apply_kernel<{k + 1}, {'double' if headp == 'f64' else 'float'}, CURVED>"},
     }
