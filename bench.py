@@ -237,12 +237,13 @@ def main():
 
     del flush
     hbm = measure_hbm(torch)
-    variants = merged = positions = advection = hermite = degrees = None
+    variants = merged = positions = advection = hermite = degrees = shard = None
     if args.variants:
         merged = bench_merged(dg, torch, synth, N, k, args.steps, args.warmup, res)
         positions = bench_merged(dg, torch, synth, N, k, args.steps, args.warmup, res, storage="positions")
         hermite = bench_hermite(dg, torch, synth, N, k, args.steps, args.warmup, res)
         advection = bench_advection(dg, torch, synth, N, k, args.steps, args.warmup)
+        shard = bench_shard(dg, torch, synth, k, args.steps, args.warmup)
         variants = bench_variants(dg, torch, synth, k)
         degrees = bench_degrees(dg, torch, synth)
 
@@ -312,6 +313,8 @@ def main():
         line["hermite_basis"] = hermite
     if advection:
         line["advection"] = advection
+    if shard:
+        line["shard"] = shard
     if variants:
         line["geometry_variants"] = variants
     if degrees:
@@ -435,6 +438,66 @@ def bench_hermite(dg, torch, synth, ncell, k, steps, warmup, g3):
             out[geo][prec] = r
             del x, y
         op.close()
+    return out
+
+
+def bench_shard(dg, torch, synth, k, steps, warmup, ncell=64, parts=8):
+    """One GPU's share of the 64^3 sine-curved mesh (variable c, G3) cut into
+    `parts` z-slabs: a 64 x 64 x 8 slab with both z sides ghost.  A step is
+    what that GPU computes per apply: the face traces of its two z sides
+    (sent to its neighbours) and the apply with the traces it received.  The
+    transfer itself is not part of a one-GPU run."""
+    nz = ncell // parts
+    z0 = nz * (parts // 2 - 1)
+    op = dg.Operator((ncell, ncell, nz), k, curved=True, amplitude=synth.AMPLITUDE, variable_coef=True,
+                     bc=(0, 0, 0, 0, dg.GHOST, dg.GHOST), lo=(0.0, 0.0, z0 / ncell), hi=(1.0, 1.0, (z0 + nz) / ncell))
+    nd = op.n_dofs
+    n = k + 1
+    plane = ncell * ncell
+    out = {"workload": f"{ncell}x{ncell}x{nz} slab (z in [{z0}/{ncell}, {z0 + nz}/{ncell})) of the {ncell}^3 "
+                       f"sine-curved mesh, k={k}, variable c, G3, ghost z sides; step = 2 trace launches + ghost apply",
+           "n_dofs": nd, "halo_values_per_side": plane * 2 * n * n}
+    cells = plane * nz
+    faces = 2 * (ncell + 1) * ncell * nz + plane * (nz + 1)
+    for prec in ("f64", "f32"):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        rb = 8 if prec == "f64" else 4
+        own = torch.from_numpy(synth.src_vector(nd, synth.seed_for(3, k))).to(dtype=dt, device="cuda")
+        nbr = torch.from_numpy(synth.src_vector(nd, synth.seed_for(3, k) + 1)).to(dtype=dt, device="cuda")
+        ghost = {4: op.face_traces(5, nbr), 5: op.face_traces(4, nbr)}
+        sent = {4: torch.empty_like(ghost[4]), 5: torch.empty_like(ghost[5])}
+        y = torch.empty_like(own)
+
+        def step():
+            op.face_traces(4, own, sent[4])
+            op.face_traces(5, own, sent[5])
+            op.apply_ghost(own, ghost, y)
+
+        def timed(fn):
+            for _ in range(warmup):
+                fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(steps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / steps
+
+        ms_step = timed(step)
+        ms_apply = timed(lambda: op.apply_ghost(own, ghost, y))
+        halo = 2 * plane * 2 * n * n
+        # src + dst + G3 cell and face geometry + traces received; the trace
+        # launches add their layers' reads and the traces sent
+        apply_bytes = (2 + 10) * cells * n ** 3 * rb + 4 * faces * n * n * rb + halo * rb
+        trace_bytes = 2 * plane * n ** 3 * rb + halo * rb
+        out[prec] = {"us_per_step": ms_step * 1e3, "us_apply": ms_apply * 1e3, "dofs_per_s": nd / (ms_step * 1e-3),
+                     "apply_algorithmic_bytes": apply_bytes, "trace_algorithmic_bytes": trace_bytes,
+                     "frac": (apply_bytes + trace_bytes) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "apply_frac": apply_bytes / (ms_apply * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del own, nbr, ghost, sent, y
+    op.close()
     return out
 
 

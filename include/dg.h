@@ -56,9 +56,14 @@ typedef enum {
 } dg_status;
 
 typedef enum { DG_F64 = 0, DG_F32 = 1 } dg_dtype;
-typedef enum { DG_BC_DIRICHLET = 0, DG_BC_NEUMANN = 1 } dg_bc;
+/* DG_BC_GHOST marks a side where the brick is one partition of a larger
+ * mesh: its faces there are interior faces of the larger mesh, and the
+ * neighbour's side of them arrives as face traces (see dg_face_traces and
+ * dg_apply_ghost).  SIPG ops only. */
+typedef enum { DG_BC_DIRICHLET = 0, DG_BC_NEUMANN = 1, DG_BC_GHOST = 2 } dg_bc;
 
-/* Structured brick; bc order x-, x+, y-, y+, z-, z+. */
+/* Structured brick; bc order x-, x+, y-, y+, z-, z+ (side f = 2a + s: the
+ * side of direction a at its low (s = 0) or high (s = 1) end). */
 typedef struct {
   int32_t ncell[3];
   double lo[3], hi[3];
@@ -189,7 +194,7 @@ dg_status dg_footprint_advection(const dg_mesh *mesh, int degree, const dg_geome
  *   y_i = -(grad phi_i, c u_h)_e + <phi_i, 1/2 (c.n)(u- + u+) + 1/2 |c.n| (u- - u+)>_{de}.
  * Boundary faces take u+ = -u- (mirror, homogeneous inflow data) where
  * mesh->bc is DG_BC_DIRICHLET and u+ = u- (outflow) where it is
- * DG_BC_NEUMANN.  geom->storage is ignored.  The op works with dg_apply,
+ * DG_BC_NEUMANN; a DG_BC_GHOST side is DG_ERR_UNSUPPORTED.  geom->storage is ignored.  The op works with dg_apply,
  * dg_n_dofs and dg_destroy; dg_diagonal, dg_rhs, dg_error_manufactured,
  * dg_cg_solve and dg_batch_admit return DG_ERR_UNSUPPORTED for it (the
  * operator is not symmetric). */
@@ -207,6 +212,49 @@ int64_t dg_n_dofs(const dg_op *op);
  * the op, length dg_n_dofs, and must not alias: otherwise DG_ERR_ARG and nothing
  * is enqueued. */
 dg_status dg_apply(dg_op *op, dg_vec src, dg_vec dst, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * One partition of a larger mesh.  Sec. 2's operator couples a cell to its
+ * face neighbours only through the neighbour's value and normal derivative
+ * on the shared face (the S_f and D_f rows of Eq. (7) applied to the
+ * neighbour's coefficients).  A partition whose side f is DG_BC_GHOST takes
+ * those two quantities for every face of side f from a trace buffer that the
+ * neighbouring partition computed with dg_face_traces; with the traces of
+ * the same global vector, dg_apply_ghost gives the rows of the global A u
+ * that the partition owns (up to the rounding of its geometry, which is
+ * evaluated from its own box).
+ *
+ * Trace layout of side f = 2a + s, for a brick with tangential cell counts
+ * (m1, m2) on that side (the two directions other than a, in increasing
+ * order): (p * 2 + r) * n^2 + j, with p = c1 + m1 * c2 the cell's position
+ * in the side's plane, r = 0 the value and r = 1 the reference normal
+ * derivative d/dxi_a, and j = j1 + n * j2 the face node (the cell's node
+ * indices along the two tangential directions).  Length 2 m1 m2 n^2.
+ * ------------------------------------------------------------------------ */
+
+/* traces := the face traces of the op's cells on side `side` (0..5) that the
+ * partition across that side needs for its own ghost side (the opposite
+ * side of the same direction): for side 2a + 1 the value and the xi_a
+ * derivative at xi_a = 1 of every cell in the last layer, for side 2a at
+ * xi_a = 0 of the first layer.  src: length dg_n_dofs; traces: the layout
+ * above, same dtype as src.  Reads no geometry, so the op need not have the
+ * precision enabled and the side's bc does not matter.  SIPG ops (either
+ * basis); DG_ERR_UNSUPPORTED for advection ops, DG_ERR_ARG for a bad side,
+ * length or dtype, or traces overlapping src; nothing is enqueued then. */
+dg_status dg_face_traces(const dg_op *op, int side, dg_vec src, dg_vec traces, void *stream);
+
+/* dst := the partition's rows of A u, like dg_apply, with every
+ * DG_BC_GHOST side's neighbour values taken from ghost[f] (the trace layout
+ * above, the neighbour's dg_face_traces of the opposite side, same dtype as
+ * src).  ghost[f] is read only where bc[f] is DG_BC_GHOST and may be
+ * {NULL, ...} elsewhere; an op with no ghost side behaves as dg_apply.
+ * DG_ERR_ARG (nothing enqueued) for a missing or mis-sized trace buffer, a
+ * wrong dtype, or a trace buffer that overlaps dst.  dg_apply returns
+ * DG_ERR_ARG for an op that has a ghost side, and dg_cg_solve and
+ * dg_batch_admit return DG_ERR_UNSUPPORTED for one (each apply would need
+ * a fresh exchange).  The Jacobi diagonal (dg_diagonal), the load vector and
+ * the error norms of such an op treat the ghost faces as interior faces. */
+dg_status dg_apply_ghost(dg_op *op, dg_vec src, const dg_vec ghost[6], dg_vec dst, void *stream);
 
 /* diag := diagonal of A (in diag.dtype), the Jacobi preconditioner. */
 dg_status dg_diagonal(dg_op *op, dg_vec diag, void *stream);

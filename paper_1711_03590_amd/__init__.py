@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libdg.so")
 
 DG_OK, DG_ERR_ARG, DG_ERR_OOM, DG_ERR_HIP, DG_ERR_UNSUPPORTED, DG_ERR_NOT_CONVERGED = range(6)
 F64, F32 = 0, 1
-DIRICHLET, NEUMANN = 0, 1
+DIRICHLET, NEUMANN, GHOST = 0, 1, 2
 MAP_AFFINE, MAP_SINE = 0, 1
 STORE_JACOBIAN, STORE_MERGED, STORE_MIXED, STORE_POSITIONS = 0, 1, 2, 3
 
@@ -123,6 +123,8 @@ _SIGS = [
                                           ctypes.POINTER(_P)]),
     ("dg_n_dofs", ctypes.c_int64, [_P]),
     ("dg_apply", ctypes.c_int, [_P, Vec, Vec, _P]),
+    ("dg_face_traces", ctypes.c_int, [_P, ctypes.c_int, Vec, Vec, _P]),
+    ("dg_apply_ghost", ctypes.c_int, [_P, Vec, ctypes.POINTER(Vec), Vec, _P]),
     ("dg_diagonal", ctypes.c_int, [_P, Vec, _P]),
     ("dg_rhs", ctypes.c_int, [_P, Vec, _P]),
     ("dg_error_manufactured", ctypes.c_int, [_P, Vec, _P, ctypes.POINTER(ctypes.c_double)]),
@@ -321,6 +323,33 @@ class Operator:
         if dst is None:
             dst = torch.empty_like(src)
         check(lib().dg_apply(self._h, vec(src), vec(dst), _stream(stream)))
+        return dst
+
+    def side_cells(self, side):
+        """Cells in the plane of side 0..5 (x-, x+, y-, y+, z-, z+)."""
+        a = side // 2
+        return self.ncell[1 if a == 0 else 0] * self.ncell[1 if a == 2 else 2]
+
+    def face_traces(self, side, src, out=None, stream=None):
+        """Value and normal derivative of src on every face of side `side`,
+        as the partition across that side reads them on its ghost side."""
+        torch = _torch()
+        if out is None:
+            n = self.degree + 1
+            out = torch.empty(self.side_cells(side) * 2 * n * n, dtype=src.dtype, device=src.device)
+        check(lib().dg_face_traces(self._h, side, vec(src), vec(out), _stream(stream)))
+        return out
+
+    def apply_ghost(self, src, ghost, dst=None, stream=None):
+        """dst = this partition's rows of A u; ghost maps each ghost side
+        (0..5) to the neighbour's face traces of that face plane."""
+        torch = _torch()
+        if dst is None:
+            dst = torch.empty_like(src)
+        g = (Vec * 6)()
+        for f, t in dict(ghost).items():
+            g[f] = vec(t)
+        check(lib().dg_apply_ghost(self._h, vec(src), g, vec(dst), _stream(stream)))
         return dst
 
     def diagonal(self, dtype=None, stream=None):

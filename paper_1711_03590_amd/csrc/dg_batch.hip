@@ -311,6 +311,7 @@ dg_status dg_batch_admit(dg_batch *b, dg_op *op, dg_vec bv, dg_vec xv, const dg_
 {
   if (!b || !op || !prm || !slot) return fail(DG_ERR_ARG, "null argument");
   if (op->gk == ADVECTION) return fail(DG_ERR_UNSUPPORTED, "batched CG needs the symmetric SIPG operator");
+  if (op->ghost_sides) return fail(DG_ERR_UNSUPPORTED, "batched CG on a partition with ghost sides is not supported");
   if (op->basis != DG_BASIS_NODAL) return fail(DG_ERR_UNSUPPORTED, "batched solves serve the nodal basis");
   if (!(op->precisions & DG_PREC_F64) || !(op->precisions & DG_PREC_F32))
     return fail(DG_ERR_ARG, "batched solves need an op with FP64 and FP32 data");

@@ -60,14 +60,26 @@ template <typename Real>
 struct OpView {
   int ncell[3];
   int ncells;
-  int bc[6];                // 0 Dirichlet, 1 Neumann
+  int bc[6];                // 0 Dirichlet, 1 Neumann, 2 ghost (traces from ghost[side])
   Real inv_h[3];            // 1 / h_a (affine Jacobian)
   Real tau[3];              // (k+1)^2 / h_a
   Real c_vol;               // AFFINE_CONST: c * hx * hy * hz
   Real c_area[3];           // AFFINE_CONST: c * h_t1 * h_t2 for faces normal to a
   GeomData<Real> g;
   int reverse = 0;          // walk the cell batches last to first (set per launch)
+  const Real *ghost[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // per launch
 };
+
+constexpr int kBcGhost = 2;
+
+// position of cell ci in the plane of its faces normal to direction A
+template <int A>
+__host__ __device__ __forceinline__ int64_t side_plane_index(const int (&nc)[3], const int (&ci)[3])
+{
+  if constexpr (A == 0) return ci[1] + (int64_t)nc[1] * ci[2];
+  else if constexpr (A == 1) return ci[0] + (int64_t)nc[0] * ci[2];
+  else return ci[0] + (int64_t)nc[0] * ci[1];
+}
 
 }  // namespace dgk
 
@@ -79,6 +91,7 @@ struct dg_op {
   dg_coefficient coef;
   dg_velocity vel{};         // advection ops only
   int basis = 0;             // SIPG ops: DG_BASIS_NODAL or DG_BASIS_HERMITE
+  bool ghost_sides = false;  // some mesh.bc is DG_BC_GHOST
   mutable std::atomic<unsigned> sweeps{0};  // SIPG applies so far: odd ones walk the cells backwards
   unsigned precisions = 0;
   int gk = 0;                // geometry kind of the FP64 data (and of the op)
@@ -125,7 +138,8 @@ hipError_t launch_apply_dot(const dg_op *op, const void *src, void *dst, bool f3
 template <int N>
 int apply_workgroups(const dg_op *op);
 
-hipError_t launch_apply_any(const dg_op *op, const void *src, void *dst, bool f32, hipStream_t s);
+hipError_t launch_apply_any(const dg_op *op, const void *src, void *dst, bool f32, hipStream_t s,
+                            const void *const *ghost = nullptr);
 // dst = A src for the SIPG operator and the workgroup shares of src.dst in
 // part (apply_workgroups_any(op) entries, see DotOut)
 hipError_t launch_apply_dot_any(const dg_op *op, const void *src, void *dst, bool f32, void *part, hipStream_t s);

@@ -18,7 +18,9 @@ namespace dgk {
 // the kernels themselves are instantiated once per N in inst.hip
 #define DG_EXTERN_N(N)                                                                  \
   extern template hipError_t launch_apply<N>(const dg_op *, const void *, void *, bool, \
-                                             hipStream_t);                              \
+                                             hipStream_t, const void *const *);         \
+  extern template hipError_t launch_face_traces<N>(const dg_op *, int, const void *, void *, bool, \
+                                                   hipStream_t);                                   \
   extern template hipError_t launch_diag<N>(const dg_op *, void *, void *, hipStream_t);        \
   extern template hipError_t launch_apply_dot<N>(const dg_op *, const void *, void *, bool,    \
                                                  void *, hipStream_t);                          \
@@ -65,17 +67,18 @@ void op_free(dg_op *op, void *p)
   else (void)hipFree(p);
 }
 
-hipError_t launch_apply_any(const dg_op *op, const void *src, void *dst, bool f32, hipStream_t s)
+hipError_t launch_apply_any(const dg_op *op, const void *src, void *dst, bool f32, hipStream_t s,
+                            const void *const *ghost)
 {
   switch (op->n) {
-    case 2: return launch_apply<2>(op, src, dst, f32, s);
-    case 3: return launch_apply<3>(op, src, dst, f32, s);
-    case 4: return launch_apply<4>(op, src, dst, f32, s);
-    case 5: return launch_apply<5>(op, src, dst, f32, s);
-    case 6: return launch_apply<6>(op, src, dst, f32, s);
-    case 7: return launch_apply<7>(op, src, dst, f32, s);
-    case 8: return launch_apply<8>(op, src, dst, f32, s);
-    case 9: return launch_apply<9>(op, src, dst, f32, s);
+    case 2: return launch_apply<2>(op, src, dst, f32, s, ghost);
+    case 3: return launch_apply<3>(op, src, dst, f32, s, ghost);
+    case 4: return launch_apply<4>(op, src, dst, f32, s, ghost);
+    case 5: return launch_apply<5>(op, src, dst, f32, s, ghost);
+    case 6: return launch_apply<6>(op, src, dst, f32, s, ghost);
+    case 7: return launch_apply<7>(op, src, dst, f32, s, ghost);
+    case 8: return launch_apply<8>(op, src, dst, f32, s, ghost);
+    case 9: return launch_apply<9>(op, src, dst, f32, s, ghost);
     default: return hipErrorInvalidValue;
   }
 }
@@ -91,6 +94,21 @@ hipError_t launch_apply_dot_any(const dg_op *op, const void *src, void *dst, boo
     case 7: return launch_apply_dot<7>(op, src, dst, f32, part, s);
     case 8: return launch_apply_dot<8>(op, src, dst, f32, part, s);
     case 9: return launch_apply_dot<9>(op, src, dst, f32, part, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_face_traces_any(const dg_op *op, int side, const void *src, void *out, bool f32, hipStream_t s)
+{
+  switch (op->n) {
+    case 2: return launch_face_traces<2>(op, side, src, out, f32, s);
+    case 3: return launch_face_traces<3>(op, side, src, out, f32, s);
+    case 4: return launch_face_traces<4>(op, side, src, out, f32, s);
+    case 5: return launch_face_traces<5>(op, side, src, out, f32, s);
+    case 6: return launch_face_traces<6>(op, side, src, out, f32, s);
+    case 7: return launch_face_traces<7>(op, side, src, out, f32, s);
+    case 8: return launch_face_traces<8>(op, side, src, out, f32, s);
+    case 9: return launch_face_traces<9>(op, side, src, out, f32, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -544,7 +562,8 @@ static dg_status validate(const dg_mesh *mesh, int degree, const dg_geometry *ge
     ncells *= mesh->ncell[d];
   }
   for (int f = 0; f < 6; ++f)
-    if (mesh->bc[f] != DG_BC_DIRICHLET && mesh->bc[f] != DG_BC_NEUMANN) return fail(DG_ERR_ARG, "bad bc");
+    if (mesh->bc[f] != DG_BC_DIRICHLET && mesh->bc[f] != DG_BC_NEUMANN && mesh->bc[f] != DG_BC_GHOST)
+      return fail(DG_ERR_ARG, "bad bc");
   if (geom->map != DG_MAP_AFFINE && geom->map != DG_MAP_SINE) return fail(DG_ERR_ARG, "bad map");
   if (geom->storage != DG_STORE_JACOBIAN && geom->storage != DG_STORE_MERGED && geom->storage != DG_STORE_MIXED &&
       geom->storage != DG_STORE_POSITIONS)
@@ -650,6 +669,9 @@ dg_status dg_footprint_advection(const dg_mesh *mesh, int degree, const dg_geome
   dg_status st = validate(mesh, degree, geom, &one, precisions);
   if (st != DG_OK) return st;
   if (!vel || (vel->kind != DG_VEL_CONST && vel->kind != DG_VEL_ROTATION)) return fail(DG_ERR_ARG, "bad velocity");
+  for (int f = 0; f < 6; ++f)
+    if (mesh->bc[f] == DG_BC_GHOST)
+      return fail(DG_ERR_UNSUPPORTED, "ghost sides are implemented for the SIPG operator only");
   if (!bytes) return fail(DG_ERR_ARG, "bytes is null");
   const int64_t nc[3] = {mesh->ncell[0], mesh->ncell[1], mesh->ncell[2]};
   *bytes = footprint_bytes(nc, degree + 1, ADVECTION, ADVECTION, precisions) -
@@ -683,6 +705,9 @@ static dg_status setup_impl(const dg_mesh *mesh, int degree, int basis, const dg
 {
   dg_status st = validate(mesh, degree, geom, coef, precisions);
   if (st != DG_OK) return st;
+  bool ghost_sides = false;
+  for (int f = 0; f < 6; ++f) ghost_sides = ghost_sides || mesh->bc[f] == DG_BC_GHOST;
+  if (vel && ghost_sides) return fail(DG_ERR_UNSUPPORTED, "ghost sides are implemented for the SIPG operator only");
   if (basis != DG_BASIS_NODAL && basis != DG_BASIS_HERMITE) return fail(DG_ERR_ARG, "bad basis");
   if (basis == DG_BASIS_HERMITE && degree < 3) return fail(DG_ERR_ARG, "the Hermite-like basis needs degree >= 3");
   if (!out) return fail(DG_ERR_ARG, "out is null");
@@ -690,6 +715,7 @@ static dg_status setup_impl(const dg_mesh *mesh, int degree, int basis, const dg
   hipStream_t s = static_cast<hipStream_t>(stream);
   dg_op *op = new dg_op();
   op->mesh = *mesh;
+  op->ghost_sides = ghost_sides;
   op->degree = degree;
   op->n = degree + 1;
   op->geom = *geom;
@@ -871,7 +897,72 @@ dg_status dg_apply(dg_op *op, dg_vec src, dg_vec dst, void *stream)
   const size_t es = f32 ? 4 : 8;
   const char *a = static_cast<const char *>(src.data), *b = static_cast<const char *>(dst.data);
   if (a < b + op->ndofs * es && b < a + op->ndofs * es) return fail(DG_ERR_ARG, "src and dst alias");
+  if (op->ghost_sides) return fail(DG_ERR_ARG, "the op has ghost sides: use dg_apply_ghost");
   hipError_t e = launch_apply_any(op, src.data, dst.data, f32, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "apply kernel");
+  return DG_OK;
+}
+
+// cells in the plane of side f (the product of the two tangential counts)
+static int64_t side_cells(const dg_op *op, int f)
+{
+  const int a = f / 2;
+  return (int64_t)op->mesh.ncell[a == 0 ? 1 : 0] * op->mesh.ncell[a == 2 ? 1 : 2];
+}
+
+static bool overlap(const void *p, int64_t pbytes, const void *q, int64_t qbytes)
+{
+  const char *a = static_cast<const char *>(p), *b = static_cast<const char *>(q);
+  return a < b + qbytes && b < a + pbytes;
+}
+
+dg_status dg_face_traces(const dg_op *op, int side, dg_vec src, dg_vec traces, void *stream)
+{
+  if (!op) return fail(DG_ERR_ARG, "op is null");
+  if (op->gk == ADVECTION) return fail(DG_ERR_UNSUPPORTED, "face traces are implemented for the SIPG operator only");
+  if (side < 0 || side > 5) return fail(DG_ERR_ARG, "side must be 0..5");
+  dg_status st = check_vec(op, src, "src");
+  if (st != DG_OK) return st;
+  if (!traces.data) return fail(DG_ERR_ARG, "traces is null");
+  if (traces.dtype != src.dtype) return fail(DG_ERR_ARG, "traces and src dtypes differ");
+  const int64_t len = side_cells(op, side) * 2 * op->n * op->n;
+  if (traces.n != len) return fail(DG_ERR_ARG, "traces length is not 2 n^2 times the cells of the side");
+  const bool f32 = src.dtype == DG_F32;
+  const int64_t es = f32 ? 4 : 8;
+  if (overlap(src.data, op->ndofs * es, traces.data, len * es)) return fail(DG_ERR_ARG, "traces overlap src");
+  hipError_t e = launch_face_traces_any(op, side, src.data, traces.data, f32, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "face traces kernel");
+  return DG_OK;
+}
+
+dg_status dg_apply_ghost(dg_op *op, dg_vec src, const dg_vec ghost[6], dg_vec dst, void *stream)
+{
+  if (!op) return fail(DG_ERR_ARG, "op is null");
+  if (op->gk == ADVECTION) return fail(DG_ERR_UNSUPPORTED, "ghost sides are implemented for the SIPG operator only");
+  dg_status st = check_vec(op, src, "src");
+  if (st != DG_OK) return st;
+  if ((st = check_vec(op, dst, "dst")) != DG_OK) return st;
+  if (src.dtype != dst.dtype) return fail(DG_ERR_ARG, "src and dst dtypes differ");
+  const bool f32 = src.dtype == DG_F32;
+  if (!(op->precisions & (f32 ? DG_PREC_F32 : DG_PREC_F64)))
+    return fail(DG_ERR_ARG, "the op was not set up for this precision");
+  const int64_t es = f32 ? 4 : 8;
+  if (overlap(src.data, op->ndofs * es, dst.data, op->ndofs * es)) return fail(DG_ERR_ARG, "src and dst alias");
+  const void *gp[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  for (int f = 0; f < 6; ++f) {
+    if (op->mesh.bc[f] != DG_BC_GHOST) continue;
+    if (!ghost) return fail(DG_ERR_ARG, "ghost is null but the op has ghost sides");
+    const dg_vec &g = ghost[f];
+    const std::string name = "ghost[" + std::to_string(f) + "]";
+    if (!g.data) return fail(DG_ERR_ARG, name + " is null on a ghost side");
+    if (g.dtype != src.dtype) return fail(DG_ERR_ARG, name + " and src dtypes differ");
+    const int64_t len = side_cells(op, f) * 2 * op->n * op->n;
+    if (g.n != len) return fail(DG_ERR_ARG, name + " length is not 2 n^2 times the cells of the side");
+    if (overlap(g.data, len * es, dst.data, op->ndofs * es)) return fail(DG_ERR_ARG, name + " overlaps dst");
+    gp[f] = g.data;
+  }
+  hipError_t e = launch_apply_any(op, src.data, dst.data, f32, static_cast<hipStream_t>(stream),
+                                  op->ghost_sides ? gp : nullptr);
   if (e != hipSuccess) return hip_fail(e, "apply kernel");
   return DG_OK;
 }

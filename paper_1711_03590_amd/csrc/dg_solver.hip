@@ -249,6 +249,7 @@ extern "C" dg_status dg_cg_solve(dg_op *op, dg_vec b, dg_vec x, const dg_solve_p
   const auto t0 = std::chrono::steady_clock::now();
   if (!op || !prm) return fail(DG_ERR_ARG, "null argument");
   if (op->gk == ADVECTION) return fail(DG_ERR_UNSUPPORTED, "CG needs the symmetric SIPG operator");
+  if (op->ghost_sides) return fail(DG_ERR_UNSUPPORTED, "CG on a partition with ghost sides needs an exchange per apply");
   if (!b.data || !x.data || b.n != op->ndofs || x.n != op->ndofs || b.dtype != DG_F64 || x.dtype != DG_F64)
     return fail(DG_ERR_ARG, "b and x must be FP64 vectors of length dg_n_dofs");
   if (b.data == x.data) return fail(DG_ERR_ARG, "b and x alias");

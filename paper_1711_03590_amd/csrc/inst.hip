@@ -7,7 +7,8 @@
 #endif
 
 namespace dgk {
-template hipError_t launch_apply<DG_N>(const dg_op *, const void *, void *, bool, hipStream_t);
+template hipError_t launch_apply<DG_N>(const dg_op *, const void *, void *, bool, hipStream_t, const void *const *);
+template hipError_t launch_face_traces<DG_N>(const dg_op *, int, const void *, void *, bool, hipStream_t);
 template hipError_t launch_diag<DG_N>(const dg_op *, void *, void *, hipStream_t);
 template hipError_t launch_apply_dot<DG_N>(const dg_op *, const void *, void *, bool, void *, hipStream_t);
 template int apply_workgroups<DG_N>(const dg_op *);

@@ -355,7 +355,7 @@ __device__ __forceinline__ void for_jobs(int l, bool act, F &&f)
 //   [[u]] = u- - u+, {{grad u}} = (grad u- + grad u+)/2; the average's
 //   tangential part is the tangential derivative of V = u- + u+ on the face
 //   (V = 2 u- on a Dirichlet face, where u+ = -u- but grad u+ = grad u-).
-template <int N, typename Real, int GK, int A, int BS, typename Next>
+template <int N, typename Real, int GK, int A, int BS, bool GH, typename Next>
 __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Real *Q, Real *R, Real *W, int l,
                                                const int (&ci)[3], bool act, bool valid, const Real (&nb)[2][N],
                                                Real (&fz)[4], Next &&next)
@@ -371,11 +371,15 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
   Real *dV = W + 4 * N2;  // [s][d_t1 V, d_t2 V]
   Real *Z = W;            // [s][tg_t1, tg_t2]
   Real *Z2 = W + 4 * N2;  // [s][Dco^T along t1 of tg_t1, Dco^T along t2 of tg_t2]
-  bool interior[2];
+  // with GH, a ghost side's faces are interior faces whose neighbour
+  // traces come from op.ghost instead of src
+  bool interior[2], ghost[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const int cn = ci[A] + (s ? 1 : -1);
-    interior[s] = valid && cn >= 0 && cn < op.ncell[A];
+    const bool inside = cn >= 0 && cn < op.ncell[A];
+    ghost[s] = GH && !inside && op.bc[2 * A + s] == kBcGhost;
+    interior[s] = valid && (inside || ghost[s]);
   }
   Real jg[2][3], cds[2];
   face_geometry<N, Real, GK, A>(op, ci, 0, l, jg[0], cds[0]);
@@ -398,6 +402,17 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
       der0 = madd(BT.F1[m], nb[0][m], der0);
       val1 = madd(BT.V0[m], nb[1][m], val1);
       der1 = madd(BT.F0[m], nb[1][m], der1);
+    }
+    if (GH && (ghost[0] || ghost[1])) {  // only cells on a partition's ghost side
+      const int64_t p = side_plane_index<A>(op.ncell, ci) * 2 * N2 + l;
+      if (ghost[0]) {
+        val0 = op.ghost[2 * A][p];
+        der0 = op.ghost[2 * A][p + N2];
+      }
+      if (ghost[1]) {
+        val1 = op.ghost[2 * A + 1][p];
+        der1 = op.ghost[2 * A + 1][p + N2];
+      }
     }
     X[0 * N2 + l] = val0;
     X[1 * N2 + l] = der0;
@@ -567,7 +582,7 @@ __device__ __forceinline__ Real wg_sum(Real v, Real *sh)
 
 // The fused pass over the cells of one batch (cells blk*B .. blk*B+B-1) by
 // a workgroup of TPB threads; smem holds B * (2 N^3 + WSZ) values.
-template <int N, typename Real, int GK, int TPB, bool DOT = false, int BS = BASIS_NODAL>
+template <int N, typename Real, int GK, int TPB, bool DOT = false, int BS = BASIS_NODAL, bool GH = false>
 __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *__restrict__ src,
                                             Real *__restrict__ dst, int blk, Real *smem,
                                             const DotOut<Real> &dot = DotOut<Real>{})
@@ -638,12 +653,12 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
     }
   };
   Real fz[4] = {Real(0), Real(0), Real(0), Real(0)};
-  face_direction<N, Real, GK, 0, BS>(op, Q, R, W, l, ci, act, valid, nb, fz,
+  face_direction<N, Real, GK, 0, BS, GH>(op, Q, R, W, l, ci, act, valid, nb, fz,
                                      [&] { load_neighbour_lines<N, Real, 1, BS>(op, src, cell, l, ci, nb); });
-  face_direction<N, Real, GK, 1, BS>(op, Q, R, W, l, ci, act, valid, nb, fz,
+  face_direction<N, Real, GK, 1, BS, GH>(op, Q, R, W, l, ci, act, valid, nb, fz,
                                      [&] { load_neighbour_lines<N, Real, 2, BS>(op, src, cell, l, ci, nb); });
   constexpr int PRE = (DG_GEO_PRE < NB) ? DG_GEO_PRE : NB;
-  face_direction<N, Real, GK, 2, BS>(op, Q, R, W, l, ci, act, valid, nb, fz, [&] {
+  face_direction<N, Real, GK, 2, BS, GH>(op, Q, R, W, l, ci, act, valid, nb, fz, [&] {
 #pragma unroll
     for (int k = 0; k < PRE; ++k) load_geometry(k, gbuf[k]);
   });
@@ -870,7 +885,7 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
   }
 }
 
-template <int N, typename Real, int GK, bool DOT = false, int BS = BASIS_NODAL>
+template <int N, typename Real, int GK, bool DOT = false, int BS = BASIS_NODAL, bool GH = false>
 __global__ void __launch_bounds__(Blocking<N>::TPB, (Occupancy<N, Real>::value))
 sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__restrict__ dst,
                   const DotOut<Real> dot = DotOut<Real>{})
@@ -881,7 +896,7 @@ sipg_apply_kernel(const OpView<Real> op, const Real *__restrict__ src, Real *__r
   // starts on the data the previous one touched last (still in the MALL
   // when the operand set exceeds it); the result does not depend on it
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  apply_batch<N, Real, GK, BK::TPB, DOT, BS>(op, src, dst, op.reverse ? (int)gridDim.x - 1 - b : b, smem, dot);
+  apply_batch<N, Real, GK, BK::TPB, DOT, BS, GH>(op, src, dst, op.reverse ? (int)gridDim.x - 1 - b : b, smem, dot);
 }
 
 // ---------------------------------------------------------------------------
@@ -1035,7 +1050,7 @@ sipg_diag_kernel(const OpView<double> op, double *__restrict__ d64, float *__res
     for (int s = 0; s < 2; ++s) {
       if (id[a] != (s ? N - 1 : 0)) continue;
       const int cn = ci[a] + (s ? 1 : -1);
-      const bool interior = cn >= 0 && cn < op.ncell[a];
+      const bool interior = (cn >= 0 && cn < op.ncell[a]) || op.bc[2 * a + s] == kBcGhost;
       double mult = 1.0;
       if (!interior) mult = (op.bc[2 * a + s] == 0) ? 2.0 : 0.0;
       if (mult == 0.0) continue;
@@ -1107,8 +1122,11 @@ __host__ void sipg_variant(const dg_op *op, bool f32, F &&f)
   with_gk(std::integral_constant<int, BASIS_NODAL>{});
 }
 
+// ghost: per side, the trace buffer read where mesh.bc is DG_BC_GHOST (an
+// array of 6 device pointers of the vectors' type, or null when no side is)
 template <int N>
-hipError_t launch_apply(const dg_op *op, const void *src, void *dst, bool f32, hipStream_t s)
+hipError_t launch_apply(const dg_op *op, const void *src, void *dst, bool f32, hipStream_t s,
+                        const void *const *ghost)
 {
   using BK = Blocking<N>;
   const int grid = (int)((op->ncells + BK::B - 1) / BK::B);
@@ -1123,6 +1141,16 @@ hipError_t launch_apply(const dg_op *op, const void *src, void *dst, bool f32, h
     }
     auto v = view;
     v.reverse = (int)(op->sweeps.fetch_add(1, std::memory_order_relaxed) & 1u);
+    if (ghost) {
+      // ops with ghost sides run their own instantiation, so that the
+      // others carry no trace of it
+      for (int f = 0; f < 6; ++f) v.ghost[f] = static_cast<const Real *>(ghost[f]);
+      sipg_variant<N>(op, f32, [&](auto gk, auto bs) {
+        hipLaunchKernelGGL((sipg_apply_kernel<N, Real, decltype(gk)::value, false, decltype(bs)::value, true>),
+                           dim3(grid), dim3(BK::TPB), 0, s, v, x, y, DotOut<Real>{});
+      });
+      return;
+    }
     sipg_variant<N>(op, f32, [&](auto gk, auto bs) {
       hipLaunchKernelGGL((sipg_apply_kernel<N, Real, decltype(gk)::value, false, decltype(bs)::value>), dim3(grid),
                          dim3(BK::TPB), 0, s, v, x, y, DotOut<Real>{});
@@ -1177,6 +1205,84 @@ hipError_t launch_diag(const dg_op *op, void *diag64, void *diag32, hipStream_t 
     hipLaunchKernelGGL((sipg_diag_kernel<N, decltype(gk)::value, decltype(bs)::value>), dim3(grid), dim3(block), 0, s,
                        op->v64, d64, d32);
   });
+  return hipGetLastError();
+}
+
+// Face traces of side 2A + s for the partition across it: for every cell of
+// the side's layer and face node l, the value and the reference normal
+// derivative at xi_A = s, i.e. the S_f and D_f rows of Eq. (7) applied to
+// the cell's normal line through l.  These are the products, in the same
+// order, that a cell of the neighbouring partition forms from an in-memory
+// neighbour (the face pass, S1), so a ghost face sees the same numbers.
+constexpr int kTraceThreads = 256;
+template <int N, typename Real, int A, int BS>
+__global__ void __launch_bounds__(kTraceThreads)
+face_traces_kernel(const int3 nc, int s, const Real *__restrict__ src, Real *__restrict__ out, int64_t nplane)
+{
+  constexpr int N2 = N * N, N3 = N2 * N;
+  constexpr int t1 = (A == 0) ? 1 : 0, t2 = (A == 2) ? 1 : 2;
+  constexpr BasisTables<N> BT = kBasis<N, BS>;
+  const int64_t i = (int64_t)blockIdx.x * kTraceThreads + threadIdx.x;
+  if (i >= nplane * N2) return;
+  const int64_t p = i / N2;
+  const int l = (int)(i - p * N2);
+  const int n[3] = {nc.x, nc.y, nc.z};
+  int ci[3];
+  ci[t1] = (int)(p % n[t1]);
+  ci[t2] = (int)(p / n[t1]);
+  ci[A] = s ? n[A] - 1 : 0;
+  const int64_t cell = ci[0] + (int64_t)n[0] * (ci[1] + (int64_t)n[1] * ci[2]);
+  const Real *line = src + cell * N3 + line_base<N, A>(l);
+  Real val = Real(-0.0), der = Real(-0.0);
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    // the high side (s = 1) is the xi_A = 1 end: V1, F1; the low side V0, F0
+    const double v = s ? BT.V1[m] : BT.V0[m], f = s ? BT.F1[m] : BT.F0[m];
+    const Real u = (v != 0.0 || f != 0.0) ? line[m * kStride<N, A>] : Real(0);
+    if (s) {
+      val = madd(BT.V1[m], u, val);
+      der = madd(BT.F1[m], u, der);
+    } else {
+      val = madd(BT.V0[m], u, val);
+      der = madd(BT.F0[m], u, der);
+    }
+  }
+  out[p * 2 * N2 + l] = val;
+  out[p * 2 * N2 + N2 + l] = der;
+}
+
+template <int N>
+hipError_t launch_face_traces(const dg_op *op, int side, const void *src, void *out, bool f32, hipStream_t s)
+{
+  const int a = side / 2, hi = side % 2;
+  const int t1 = (a == 0) ? 1 : 0, t2 = (a == 2) ? 1 : 2;
+  const int64_t nplane = (int64_t)op->mesh.ncell[t1] * op->mesh.ncell[t2];
+  const int64_t threads = nplane * N * N;
+  const int grid = (int)((threads + kTraceThreads - 1) / kTraceThreads);
+  const int3 nc = make_int3(op->mesh.ncell[0], op->mesh.ncell[1], op->mesh.ncell[2]);
+  auto go = [&](auto zero, auto bs) {
+    using Real = decltype(zero);
+    constexpr int BS = decltype(bs)::value;
+    const Real *x = static_cast<const Real *>(src);
+    Real *y = static_cast<Real *>(out);
+    switch (a) {
+      case 0: hipLaunchKernelGGL((face_traces_kernel<N, Real, 0, BS>), dim3(grid), dim3(kTraceThreads), 0, s, nc, hi, x, y, nplane); break;
+      case 1: hipLaunchKernelGGL((face_traces_kernel<N, Real, 1, BS>), dim3(grid), dim3(kTraceThreads), 0, s, nc, hi, x, y, nplane); break;
+      default: hipLaunchKernelGGL((face_traces_kernel<N, Real, 2, BS>), dim3(grid), dim3(kTraceThreads), 0, s, nc, hi, x, y, nplane); break;
+    }
+  };
+  auto with_basis = [&](auto zero) {
+    if constexpr (N >= 4) {
+      if (op->basis == BASIS_HERMITE) {
+        go(zero, std::integral_constant<int, BASIS_HERMITE>{});
+        return;
+      }
+    }
+    go(zero, std::integral_constant<int, BASIS_NODAL>{});
+  };
+  if (grid == 0) return hipSuccess;
+  if (f32) with_basis(0.0f);
+  else with_basis(0.0);
   return hipGetLastError();
 }
 

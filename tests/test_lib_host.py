@@ -200,3 +200,21 @@ def test_footprint_positions_storage(dg):
     faces = 3 * N * N * (N + 1)
     vals = 4 * cells * n ** 3 + 4 * faces * n ** 2 + cells * n ** 3
     assert dg.footprint(N, k, curved=True, storage="positions") == vals * 12
+
+
+def test_ghost_sides_validation(dg):
+    """DG_BC_GHOST is a valid side for the SIPG operator (same footprint as a
+    Dirichlet side), rejected for advection; the partition calls reject a
+    null op before touching the device."""
+    import ctypes
+    ghost = (dg.DIRICHLET,) * 4 + (dg.GHOST, dg.GHOST)
+    assert dg.footprint(6, 3, curved=True, bc=ghost) == dg.footprint(6, 3, curved=True)
+    with pytest.raises(dg.DGError) as e:
+        dg.footprint(6, 3, bc=(dg.DIRICHLET,) * 5 + (3,))
+    assert e.value.status == dg.DG_ERR_ARG
+    with pytest.raises(dg.DGError) as e:
+        dg.footprint_advection(6, 3, bc=ghost)
+    assert e.value.status == dg.DG_ERR_UNSUPPORTED
+    v = dg.Vec(None, dg.F64, 0)
+    assert dg.lib().dg_face_traces(None, 0, v, v, None) == dg.DG_ERR_ARG
+    assert dg.lib().dg_apply_ghost(None, v, (dg.Vec * 6)(), v, None) == dg.DG_ERR_ARG
