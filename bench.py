@@ -200,8 +200,8 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one MI355X; runs on more than one GPU are not "
-              "supported (the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py: measures one MI355X only; runs on more than one GPU are not supported "
+              "(the one-GPU share of a sharded apply is the 'shard' entry of the output)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
