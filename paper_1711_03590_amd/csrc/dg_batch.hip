@@ -2,12 +2,14 @@
 //
 // A batch holds up to max_slots requests, each a reliable-update mixed CG
 // (dg_cg_solve mode 2) on its own operator.  dg_batch_run advances all
-// active requests by one CG iteration per round; a round is four launches:
-//   1. one persistent apply kernel whose workgroups walk a list of
-//      (request, cell batch) items spanning every active request, whatever
-//      its degree or geometry (q = A p in FP32);
-//   2.-4. batched BLAS kernels over (request, chunk) items: p.q partials,
-//      the x/r update with r.z, r.r partials, the p update.
+// active requests by one CG iteration per round; a round is:
+//   1. per degree present, one persistent apply kernel whose workgroups walk
+//      a list of (request, cell batch) items spanning every active request
+//      of that degree, whatever its size or geometry (q = A p in FP32, and
+//      each item's share of p.q);
+//   2. the sum of each request's p.q shares, in item order;
+//   3.-4. two batched BLAS kernels over (request, chunk) items of all
+//      requests: the x/r update with r.z, r.r partials, and the p update.
 // Each request's sums are taken over the same fixed partition of its own
 // vectors as in dg_cg_solve, and its check points count its own iterations,
 // so its result does not depend on the other requests in the batch.  The
@@ -45,8 +47,17 @@ DG_EXTERN_N(9)
 constexpr int kBatchTpb = 256;
 // degrees served by the persistent kernel: 2..7 (3..8 points per direction)
 constexpr int kBatchMinN = 3, kBatchMaxN = 8;
+// workgroups of the persistent apply launch (a multiple of kXcds)
+#ifndef DG_BATCH_GRID
+#define DG_BATCH_GRID 2048
+#endif
+constexpr int kXcds = 8;   // XCDs of an MI355X
+static_assert(DG_BATCH_GRID % kXcds == 0, "the persistent grid is a multiple of the XCD count");
 #ifndef DG_BATCH_WAVES
 #define DG_BATCH_WAVES 4
+#endif
+#ifndef DG_BATCH_WAVES_HI
+#define DG_BATCH_WAVES_HI 3
 #endif
 
 template <int N>
@@ -55,9 +66,12 @@ constexpr int batch_lds()
   using BK = Blocking<N, kBatchTpb>;
   return BK::SMEM;
 }
-constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int kBatchLds = cmax(cmax(cmax(batch_lds<3>(), batch_lds<4>()), cmax(batch_lds<5>(), batch_lds<6>())),
-                               cmax(batch_lds<7>(), batch_lds<8>()));
+template <int N>
+constexpr int kBatchLds = batch_lds<N>();
+// occupancy target (waves per SIMD, i.e. workgroups per CU) given to the
+// compiler: degrees 5 to 7 need more registers than 4 waves leave
+template <int N>
+constexpr int kBatchWaves = N >= 6 ? DG_BATCH_WAVES_HI : DG_BATCH_WAVES;
 
 // device descriptor of one active request
 struct BatchSlot {
@@ -68,42 +82,66 @@ struct BatchSlot {
   int round0;          // batch round of the request's first iteration
   float *e, *r, *p, *q;
   const float *d;
-  float *part;         // kRedBlocks p.q partials, 2 kRedBlocks r.z/r.r partials, scal[4]
+  float *part;         // kRedBlocks p.q partials (entry 0 the sum, the others zero), 2 kRedBlocks r.z/r.r partials, scal[4]
+  float *share;        // per item: its workgroup's share of p.q, written by the apply
 };
 
-// one function per degree (not inlined into the persistent kernel), so that
-// each degree's register allocation stays its own
-template <int N>
-__device__ __noinline__ void batch_apply_one(const BatchSlot &sl, int blk, float *smem)
+// A pointer read from the slot table is a generic pointer to the compiler
+// (only kernel arguments are known to point to global memory), so every
+// access through it would be a flat access, which waits on the LDS counter
+// as well and keeps global loads from overlapping LDS work.  Rebuilding it
+// from its integer value as a global pointer lets the accesses be global.
+template <typename T>
+__device__ __forceinline__ T *as_global(T *p)
 {
+  typedef __attribute__((address_space(1))) T GT;
+  return (T *)(GT *)(uintptr_t)p;
+}
+
+// the apply of one item, inlined into its degree's persistent kernel
+template <int N>
+__device__ __forceinline__ void batch_apply_one(const BatchSlot &sl, int blk, float *smem)
+{
+  const OpView<float> &v = sl.v;
+  const float *p = as_global(sl.p);
+  float *q = as_global(sl.q);
+  const DotOut<float> dot{as_global(sl.share)};
   switch (sl.gk) {
-    case CURVED: apply_batch<N, float, CURVED, kBatchTpb>(sl.v, sl.p, sl.q, blk, smem); break;
-    case CURVED_MERGED: apply_batch<N, float, CURVED_MERGED, kBatchTpb>(sl.v, sl.p, sl.q, blk, smem); break;
-    case CURVED_POS: apply_batch<N, float, CURVED_POS, kBatchTpb>(sl.v, sl.p, sl.q, blk, smem); break;
-    case AFFINE_VAR: apply_batch<N, float, AFFINE_VAR, kBatchTpb>(sl.v, sl.p, sl.q, blk, smem); break;
-    default: apply_batch<N, float, AFFINE_CONST, kBatchTpb>(sl.v, sl.p, sl.q, blk, smem); break;
+    case CURVED: apply_batch<N, float, CURVED, kBatchTpb, true>(v, p, q, blk, smem, dot); break;
+    case CURVED_MERGED: apply_batch<N, float, CURVED_MERGED, kBatchTpb, true>(v, p, q, blk, smem, dot); break;
+    case CURVED_POS: apply_batch<N, float, CURVED_POS, kBatchTpb, true>(v, p, q, blk, smem, dot); break;
+    case AFFINE_VAR: apply_batch<N, float, AFFINE_VAR, kBatchTpb, true>(v, p, q, blk, smem, dot); break;
+    default: apply_batch<N, float, AFFINE_CONST, kBatchTpb, true>(v, p, q, blk, smem, dot); break;
   }
 }
 
-// persistent: workgroup b takes items b, b + G, b + 2G, ... (G = gridDim.x);
-// every workgroup leaves the loop once the item list is exhausted
-__global__ void __launch_bounds__(kBatchTpb, DG_BATCH_WAVES) batch_apply_kernel(const BatchSlot *__restrict__ slots, int nslots,
-                                                                int nitems)
+// Persistent and XCD-aware, one kernel per degree: the kernel for N walks
+// the items [item_begin, item_end) of the requests of that degree (the
+// descriptors are ordered by degree, so these are contiguous).
+// Workgroups are dispatched to the 8 XCDs round robin (workgroup b to XCD
+// b mod 8), so the range is cut into 8 contiguous pieces and the G/8
+// workgroups of XCD x walk piece x with stride G/8: neighbouring cell
+// batches, which share neighbour blocks and face geometry, then run at about
+// the same time on one XCD and meet in its L2.  G is a multiple of 8; every
+// workgroup leaves its loop at the end of its piece.  One kernel per degree
+// (rather than one kernel calling a function per degree) keeps the apply
+// inlined: a call would save and restore the callee-saved registers through
+// scratch memory on every item.
+template <int N>
+__global__ void __launch_bounds__(kBatchTpb, (kBatchWaves<N>))
+batch_apply_kernel(const BatchSlot *__restrict__ slots, int nslots, int slot0, int item_begin, int item_end)
 {
-  __shared__ float smem[kBatchLds];
-  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
-    int s = 0;
+  __shared__ float smem[kBatchLds<N>];
+  constexpr int X = kXcds;
+  const int xcd = blockIdx.x % X, w = blockIdx.x / X, nw = gridDim.x / X;
+  const int nitems = item_end - item_begin;
+  const int per = (nitems + X - 1) / X;
+  const int lo = item_begin + xcd * per, hi = min(item_end, lo + per);
+  for (int item = lo + w; item < hi; item += nw) {
+    int s = slot0;
     while (s + 1 < nslots && slots[s + 1].item0 <= item) ++s;
     const BatchSlot &sl = slots[s];
-    const int blk = item - sl.item0;
-    switch (sl.n) {
-      case 3: batch_apply_one<3>(sl, blk, smem); break;
-      case 4: batch_apply_one<4>(sl, blk, smem); break;
-      case 5: batch_apply_one<5>(sl, blk, smem); break;
-      case 6: batch_apply_one<6>(sl, blk, smem); break;
-      case 7: batch_apply_one<7>(sl, blk, smem); break;
-      default: batch_apply_one<8>(sl, blk, smem); break;
-    }
+    batch_apply_one<N>(sl, item - sl.item0, smem);
     __syncthreads();
   }
 }
@@ -112,11 +150,13 @@ __global__ void __launch_bounds__(kBatchTpb, DG_BATCH_WAVES) batch_apply_kernel(
 // iteration count: iteration it uses scal[it & 1])
 __device__ __forceinline__ int batch_cur(const BatchSlot &sl, int round) { return (round - sl.round0 + 1) & 1; }
 
-__global__ void __launch_bounds__(kRedThreads) batch_dot_kernel(const BatchSlot *__restrict__ slots)
+// p.q of every request: the sum of its items' shares in item order, into
+// part[0] (the other p.q partials stay zero)
+__global__ void __launch_bounds__(kSumThreads) batch_shares_kernel(const BatchSlot *__restrict__ slots)
 {
-  __shared__ float sh[kRedThreads];
-  const BatchSlot &sl = slots[blockIdx.x / kRedBlocks];
-  dot_partial_body<float, float>(sl.p, sl.q, sl.ndofs, sl.part, blockIdx.x % kRedBlocks, sh);
+  __shared__ float sh[kSumThreads];
+  const BatchSlot &sl = slots[blockIdx.x];
+  sum_shares_body<float>(sl.share, sl.nitems, sl.part, sh);
 }
 
 __global__ void __launch_bounds__(kRedThreads) batch_update_kernel(const BatchSlot *__restrict__ slots, int round)
@@ -154,7 +194,7 @@ struct Request {
   int it = 0;           // CG iterations done
   int round0 = 0;
   void *mem[8] = {nullptr};
-  float *e = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *part = nullptr;
+  float *e = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *part = nullptr, *share = nullptr;
   double *r64 = nullptr, *dpart = nullptr;
   dg_solve_stats st{};
   std::chrono::steady_clock::time_point t0;
@@ -174,8 +214,10 @@ struct dg_batch {
   double *h_scalar = nullptr;
   int round = 0;
   bool dirty = true;
-  std::vector<int> active;   // request index per descriptor position
+  std::vector<int> active;   // request index per descriptor position (ordered by degree)
   int nitems = 0;
+  // per number of points n: descriptors [slot0[n], ...) and items [item0[n], item1[n])
+  int slot0[kBatchMaxN + 1] = {}, item0[kBatchMaxN + 1] = {}, item1[kBatchMaxN + 1] = {};
 };
 
 namespace {
@@ -236,27 +278,33 @@ dg_status rebuild(dg_batch *b, hipStream_t s)
 {
   b->active.clear();
   int item = 0;
-  for (int i = 0; i < b->max_slots; ++i) {
-    Request &r = b->req[i];
-    if (!r.used || r.done) continue;
-    BatchSlot &d = b->h_desc[b->active.size()];
-    const int n = r.op->n;
-    const int cells_per_item = kBatchTpb / (n * n);
-    d.v = r.op->v32;
-    d.n = n;
-    d.gk = r.op->gk32;
-    d.ndofs = r.op->ndofs;
-    d.item0 = item;
-    d.nitems = (int)((r.op->ncells + cells_per_item - 1) / cells_per_item);
-    d.round0 = r.round0;
-    d.e = r.e;
-    d.r = r.r;
-    d.p = r.p;
-    d.q = r.q;
-    d.d = static_cast<const float *>(r.op->diag[1]);
-    d.part = r.part;
-    item += d.nitems;
-    b->active.push_back(i);
+  // descriptors ordered by degree, so that each degree's items are contiguous
+  for (int n = kBatchMinN; n <= kBatchMaxN; ++n) {
+    b->slot0[n] = (int)b->active.size();
+    b->item0[n] = item;
+    for (int i = 0; i < b->max_slots; ++i) {
+      Request &r = b->req[i];
+      if (!r.used || r.done || r.op->n != n) continue;
+      BatchSlot &d = b->h_desc[b->active.size()];
+      const int cells_per_item = kBatchTpb / (n * n);
+      d.v = r.op->v32;
+      d.n = n;
+      d.gk = r.op->gk32;
+      d.ndofs = r.op->ndofs;
+      d.item0 = item;
+      d.nitems = (int)((r.op->ncells + cells_per_item - 1) / cells_per_item);
+      d.round0 = r.round0;
+      d.e = r.e;
+      d.r = r.r;
+      d.p = r.p;
+      d.q = r.q;
+      d.d = static_cast<const float *>(r.op->diag[1]);
+      d.part = r.part;
+      d.share = r.share;
+      item += d.nitems;
+      b->active.push_back(i);
+    }
+    b->item1[n] = item;
   }
   b->nitems = item;
   if (!b->active.empty()) {
@@ -338,9 +386,12 @@ dg_status dg_batch_admit(dg_batch *b, dg_op *op, dg_vec bv, dg_vec xv, const dg_
   r.b = static_cast<const double *>(bv.data);
   r.prm = *prm;
   const int64_t n = op->ndofs;
-  const size_t sz[7] = {n * sizeof(float), n * sizeof(float), n * sizeof(float), n * sizeof(float),
-                        (3 * kRedBlocks + 4) * sizeof(float), n * sizeof(double), (kRedBlocks + 8) * sizeof(double)};
-  for (int i = 0; i < 7; ++i) {
+  const int64_t cells_per_item = kBatchTpb / (op->n * op->n);
+  const int64_t items = (op->ncells + cells_per_item - 1) / cells_per_item;
+  const size_t sz[8] = {n * sizeof(float), n * sizeof(float), n * sizeof(float), n * sizeof(float),
+                        (3 * kRedBlocks + 4) * sizeof(float), n * sizeof(double), (kRedBlocks + 8) * sizeof(double),
+                        (size_t)items * sizeof(float)};
+  for (int i = 0; i < 8; ++i) {
     r.mem[i] = balloc(b, sz[i]);
     if (!r.mem[i]) {
       release(b, r);
@@ -354,7 +405,10 @@ dg_status dg_batch_admit(dg_batch *b, dg_op *op, dg_vec bv, dg_vec xv, const dg_
   r.part = static_cast<float *>(r.mem[4]);
   r.r64 = static_cast<double *>(r.mem[5]);
   r.dpart = static_cast<double *>(r.mem[6]);
+  r.share = static_cast<float *>(r.mem[7]);
   r.used = true;
+  // the p.q partials past entry 0 stay zero (entry 0 takes the sum of the shares)
+  hipLaunchKernelGGL((fill_kernel<float>), dim3(1), dim3(kRedThreads), 0, s, r.part, 0.0f, (int64_t)kRedBlocks);
   // ||b||, then the first FP64 residual and search direction
   double *dscal = r.dpart + kRedBlocks;
   hipLaunchKernelGGL((dot_partial_kernel<double, double>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, r.b, r.b, n,
@@ -403,9 +457,23 @@ dg_status dg_batch_run(dg_batch *b, int max_rounds, void *stream)
     const int na = (int)b->active.size();
     if (na == 0) break;
     b->round += 1;
-    const int grid = b->nitems < 2048 ? b->nitems : 2048;
-    hipLaunchKernelGGL(batch_apply_kernel, dim3(grid), dim3(kBatchTpb), 0, s, b->d_desc, na, b->nitems);
-    hipLaunchKernelGGL(batch_dot_kernel, dim3(na * kRedBlocks), dim3(kRedThreads), 0, s, b->d_desc);
+    for (int n = kBatchMinN; n <= kBatchMaxN; ++n) {
+      const int items = b->item1[n] - b->item0[n];
+      if (items == 0) continue;
+      // a multiple of the XCD count, at most DG_BATCH_GRID
+      const int want = items < DG_BATCH_GRID ? items : DG_BATCH_GRID;
+      const int grid = ((want + kXcds - 1) / kXcds) * kXcds;
+      const int args[3] = {b->slot0[n], b->item0[n], b->item1[n]};
+      switch (n) {
+        case 3: hipLaunchKernelGGL(batch_apply_kernel<3>, dim3(grid), dim3(kBatchTpb), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
+        case 4: hipLaunchKernelGGL(batch_apply_kernel<4>, dim3(grid), dim3(kBatchTpb), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
+        case 5: hipLaunchKernelGGL(batch_apply_kernel<5>, dim3(grid), dim3(kBatchTpb), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
+        case 6: hipLaunchKernelGGL(batch_apply_kernel<6>, dim3(grid), dim3(kBatchTpb), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
+        case 7: hipLaunchKernelGGL(batch_apply_kernel<7>, dim3(grid), dim3(kBatchTpb), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
+        default: hipLaunchKernelGGL(batch_apply_kernel<8>, dim3(grid), dim3(kBatchTpb), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
+      }
+    }
+    hipLaunchKernelGGL(batch_shares_kernel, dim3(na), dim3(kSumThreads), 0, s, b->d_desc);
     hipLaunchKernelGGL(batch_update_kernel, dim3(na * kRedBlocks), dim3(kRedThreads), 0, s, b->d_desc, b->round);
     hipLaunchKernelGGL(batch_pupdate_kernel, dim3(na * kRedBlocks), dim3(kRedThreads), 0, s, b->d_desc, b->round);
     DG_HIP(hipGetLastError());

@@ -93,9 +93,8 @@ __global__ void __launch_bounds__(kRedThreads) finalize_kernel(const Acc *__rest
 // a fixed tree over the T = 1024 threads of the one workgroup
 constexpr int kSumThreads = 1024;
 template <typename Acc>
-__global__ void __launch_bounds__(kSumThreads) sum_shares_kernel(const Acc *__restrict__ part, int count, Acc *out)
+__device__ __forceinline__ void sum_shares_body(const Acc *__restrict__ part, int count, Acc *out, Acc *sh)
 {
-  __shared__ Acc sh[kSumThreads];
   const int t = threadIdx.x;
   Acc v = Acc(0);
   int i = t;
@@ -114,6 +113,13 @@ __global__ void __launch_bounds__(kSumThreads) sum_shares_kernel(const Acc *__re
     __syncthreads();
   }
   if (t == 0) out[0] = sh[0];
+}
+
+template <typename Acc>
+__global__ void __launch_bounds__(kSumThreads) sum_shares_kernel(const Acc *__restrict__ part, int count, Acc *out)
+{
+  __shared__ Acc sh[kSumThreads];
+  sum_shares_body(part, count, out, sh);
 }
 
 template <typename Real>
