@@ -44,7 +44,19 @@ DG_EXTERN_N(8)
 DG_EXTERN_N(9)
 #undef DG_EXTERN_N
 
-constexpr int kBatchTpb = 256;
+// threads per workgroup of the batched apply: 128 up to degree 4, 256 above
+// (measured per degree on single requests: 128 threads are 10 % faster at
+// degrees 2 and 4, 256 threads 8 to 23 % faster at degrees 6 and 7)
+#ifndef DG_BATCH_TPB_LO
+#define DG_BATCH_TPB_LO 128
+#endif
+#ifndef DG_BATCH_TPB
+#define DG_BATCH_TPB 256
+#endif
+template <int N>
+constexpr int kBatchTpb = N <= 5 ? DG_BATCH_TPB_LO : DG_BATCH_TPB;
+// the same on the host, for a runtime number of points n
+inline int batch_tpb(int n) { return n <= 5 ? DG_BATCH_TPB_LO : DG_BATCH_TPB; }
 // degrees served by the persistent kernel: 2..7 (3..8 points per direction)
 constexpr int kBatchMinN = 3, kBatchMaxN = 8;
 // workgroups of the persistent apply launch (a multiple of kXcds)
@@ -63,7 +75,7 @@ static_assert(DG_BATCH_GRID % kXcds == 0, "the persistent grid is a multiple of 
 template <int N>
 constexpr int batch_lds()
 {
-  using BK = Blocking<N, kBatchTpb>;
+  using BK = Blocking<N, kBatchTpb<N>>;
   return BK::SMEM;
 }
 template <int N>
@@ -78,7 +90,7 @@ struct BatchSlot {
   OpView<float> v;
   int n, gk;
   int64_t ndofs;
-  int item0, nitems;   // apply items [item0, item0 + nitems): cell batches of kBatchTpb / n^2 cells
+  int item0, nitems;   // apply items [item0, item0 + nitems): cell batches of batch_tpb(n) / n^2 cells
   int round0;          // batch round of the request's first iteration
   float *e, *r, *p, *q;
   const float *d;
@@ -107,11 +119,11 @@ __device__ __forceinline__ void batch_apply_one(const BatchSlot &sl, int blk, fl
   float *q = as_global(sl.q);
   const DotOut<float> dot{as_global(sl.share)};
   switch (sl.gk) {
-    case CURVED: apply_batch<N, float, CURVED, kBatchTpb, true>(v, p, q, blk, smem, dot); break;
-    case CURVED_MERGED: apply_batch<N, float, CURVED_MERGED, kBatchTpb, true>(v, p, q, blk, smem, dot); break;
-    case CURVED_POS: apply_batch<N, float, CURVED_POS, kBatchTpb, true>(v, p, q, blk, smem, dot); break;
-    case AFFINE_VAR: apply_batch<N, float, AFFINE_VAR, kBatchTpb, true>(v, p, q, blk, smem, dot); break;
-    default: apply_batch<N, float, AFFINE_CONST, kBatchTpb, true>(v, p, q, blk, smem, dot); break;
+    case CURVED: apply_batch<N, float, CURVED, kBatchTpb<N>, true>(v, p, q, blk, smem, dot); break;
+    case CURVED_MERGED: apply_batch<N, float, CURVED_MERGED, kBatchTpb<N>, true>(v, p, q, blk, smem, dot); break;
+    case CURVED_POS: apply_batch<N, float, CURVED_POS, kBatchTpb<N>, true>(v, p, q, blk, smem, dot); break;
+    case AFFINE_VAR: apply_batch<N, float, AFFINE_VAR, kBatchTpb<N>, true>(v, p, q, blk, smem, dot); break;
+    default: apply_batch<N, float, AFFINE_CONST, kBatchTpb<N>, true>(v, p, q, blk, smem, dot); break;
   }
 }
 
@@ -128,7 +140,7 @@ __device__ __forceinline__ void batch_apply_one(const BatchSlot &sl, int blk, fl
 // inlined: a call would save and restore the callee-saved registers through
 // scratch memory on every item.
 template <int N>
-__global__ void __launch_bounds__(kBatchTpb, (kBatchWaves<N>))
+__global__ void __launch_bounds__(kBatchTpb<N>, (kBatchWaves<N>))
 batch_apply_kernel(const BatchSlot *__restrict__ slots, int nslots, int slot0, int item_begin, int item_end)
 {
   __shared__ float smem[kBatchLds<N>];
@@ -286,7 +298,7 @@ dg_status rebuild(dg_batch *b, hipStream_t s)
       Request &r = b->req[i];
       if (!r.used || r.done || r.op->n != n) continue;
       BatchSlot &d = b->h_desc[b->active.size()];
-      const int cells_per_item = kBatchTpb / (n * n);
+      const int cells_per_item = batch_tpb(n) / (n * n);
       d.v = r.op->v32;
       d.n = n;
       d.gk = r.op->gk32;
@@ -386,7 +398,7 @@ dg_status dg_batch_admit(dg_batch *b, dg_op *op, dg_vec bv, dg_vec xv, const dg_
   r.b = static_cast<const double *>(bv.data);
   r.prm = *prm;
   const int64_t n = op->ndofs;
-  const int64_t cells_per_item = kBatchTpb / (op->n * op->n);
+  const int64_t cells_per_item = batch_tpb(op->n) / (op->n * op->n);
   const int64_t items = (op->ncells + cells_per_item - 1) / cells_per_item;
   const size_t sz[8] = {n * sizeof(float), n * sizeof(float), n * sizeof(float), n * sizeof(float),
                         (3 * kRedBlocks + 4) * sizeof(float), n * sizeof(double), (kRedBlocks + 8) * sizeof(double),
@@ -465,12 +477,12 @@ dg_status dg_batch_run(dg_batch *b, int max_rounds, void *stream)
       const int grid = ((want + kXcds - 1) / kXcds) * kXcds;
       const int args[3] = {b->slot0[n], b->item0[n], b->item1[n]};
       switch (n) {
-        case 3: hipLaunchKernelGGL(batch_apply_kernel<3>, dim3(grid), dim3(kBatchTpb), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
-        case 4: hipLaunchKernelGGL(batch_apply_kernel<4>, dim3(grid), dim3(kBatchTpb), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
-        case 5: hipLaunchKernelGGL(batch_apply_kernel<5>, dim3(grid), dim3(kBatchTpb), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
-        case 6: hipLaunchKernelGGL(batch_apply_kernel<6>, dim3(grid), dim3(kBatchTpb), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
-        case 7: hipLaunchKernelGGL(batch_apply_kernel<7>, dim3(grid), dim3(kBatchTpb), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
-        default: hipLaunchKernelGGL(batch_apply_kernel<8>, dim3(grid), dim3(kBatchTpb), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
+        case 3: hipLaunchKernelGGL(batch_apply_kernel<3>, dim3(grid), dim3(kBatchTpb<3>), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
+        case 4: hipLaunchKernelGGL(batch_apply_kernel<4>, dim3(grid), dim3(kBatchTpb<4>), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
+        case 5: hipLaunchKernelGGL(batch_apply_kernel<5>, dim3(grid), dim3(kBatchTpb<5>), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
+        case 6: hipLaunchKernelGGL(batch_apply_kernel<6>, dim3(grid), dim3(kBatchTpb<6>), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
+        case 7: hipLaunchKernelGGL(batch_apply_kernel<7>, dim3(grid), dim3(kBatchTpb<7>), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
+        default: hipLaunchKernelGGL(batch_apply_kernel<8>, dim3(grid), dim3(kBatchTpb<8>), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
       }
     }
     hipLaunchKernelGGL(batch_shares_kernel, dim3(na), dim3(kSumThreads), 0, s, b->d_desc);
