@@ -190,7 +190,7 @@ __device__ __forceinline__ void adv_apply_batch(const OpView<Real> &op, const Re
   constexpr int NB = (DG_GEO_BUFS < N) ? DG_GEO_BUFS : N;
   Real gbuf[NB][3];
   auto load_geometry = [&](int k, Real (&gb)[3]) {
-    const int64_t ix = (int64_t)cell * N3 + l + k * N2;
+    const int64_t ix = geo_base<N>(cell) + l + k * kGeoPlane<N>;
     const int64_t cs = op.g.cell_stride;
 #pragma unroll
     for (int m = 0; m < 3; ++m) gb[m] = op.g.cell[m * cs + ix];

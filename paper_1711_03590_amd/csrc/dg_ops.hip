@@ -234,13 +234,16 @@ __device__ __forceinline__ double coef_value(const GeoArgs &g, const double x[3]
 }
 
 template <int GK>
-__global__ void geom_cells_kernel(const GeoArgs g, int64_t npts, double *o64, float *o32, int64_t stride)
+__global__ void geom_cells_kernel(const GeoArgs g, int64_t npts, double *o64, float *o32, int64_t stride, int group)
 {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= npts) return;
-  const int n = g.rule.n, n3 = n * n * n;
+  const int n = g.rule.n, n2 = n * n, n3 = n2 * n;
   const int64_t cell = idx / n3;
   const int q = (int)(idx - cell * n3);
+  // the grouped layout the apply kernels read (geo_base / geo_off)
+  const int64_t grp = cell / group;
+  const int64_t at = ((grp * n + q / n2) * group + (cell - grp * group)) * n2 + q % n2;
   const int qi[3] = {q % n, (q / n) % n, q / (n * n)};
   const int ci[3] = {(int)(cell % g.ncell[0]), (int)((cell / g.ncell[0]) % g.ncell[1]),
                      (int)(cell / ((int64_t)g.ncell[0] * g.ncell[1]))};
@@ -254,11 +257,11 @@ __global__ void geom_cells_kernel(const GeoArgs g, int64_t npts, double *o64, fl
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) {
         const double v = Gi[b][a] / g.h[b];
-        if (o64) o64[(3 * a + b) * stride + idx] = v;
-        if (o32) o32[(3 * a + b) * stride + idx] = (float)v;
+        if (o64) o64[(3 * a + b) * stride + at] = v;
+        if (o32) o32[(3 * a + b) * stride + at] = (float)v;
       }
-    if (o64) o64[9 * stride + idx] = cjxw;
-    if (o32) o32[9 * stride + idx] = (float)cjxw;
+    if (o64) o64[9 * stride + at] = cjxw;
+    if (o32) o32[9 * stride + at] = (float)cjxw;
   } else if (GK == ADVECTION) {
     // t = J^{-1} c det J w: J^{-1}[b][c] = Ginv[b][c] / h_b
     double v[3];
@@ -266,20 +269,20 @@ __global__ void geom_cells_kernel(const GeoArgs g, int64_t npts, double *o64, fl
     const double jxw = detG * g.h[0] * g.h[1] * g.h[2] * W;
     for (int b = 0; b < 3; ++b) {
       const double t = (Gi[b][0] * v[0] + Gi[b][1] * v[1] + Gi[b][2] * v[2]) / g.h[b] * jxw;
-      if (o64) o64[b * stride + idx] = t;
-      if (o32) o32[b * stride + idx] = (float)t;
+      if (o64) o64[b * stride + at] = t;
+      if (o32) o32[b * stride + at] = (float)t;
     }
   } else if (GK == CURVED_POS) {
     // the point relative to the cell's unmapped corner (small numbers, so
     // that FP32 keeps the differences the collocation derivative takes), and c
     for (int d = 0; d < 3; ++d) {
       const double v = x[d] - (g.lo[d] + ci[d] * g.h[d]);
-      if (o64) o64[d * stride + idx] = v;
-      if (o32) o32[d * stride + idx] = (float)v;
+      if (o64) o64[d * stride + at] = v;
+      if (o32) o32[d * stride + at] = (float)v;
     }
     const double c = coef_value(g, x);
-    if (o64) o64[3 * stride + idx] = c;
-    if (o32) o32[3 * stride + idx] = (float)c;
+    if (o64) o64[3 * stride + at] = c;
+    if (o32) o32[3 * stride + at] = (float)c;
   } else if (GK == CURVED_MERGED) {
     // M = c det J w J^{-1} J^{-T}: M[b][c] = cjxw sum_a J^{-T}[a][b] J^{-T}[a][c]
     double jt[3][3];
@@ -288,12 +291,12 @@ __global__ void geom_cells_kernel(const GeoArgs g, int64_t npts, double *o64, fl
     const int rb[6] = {0, 0, 0, 1, 1, 2}, rc[6] = {0, 1, 2, 1, 2, 2};
     for (int e = 0; e < 6; ++e) {
       const double v = cjxw * (jt[0][rb[e]] * jt[0][rc[e]] + jt[1][rb[e]] * jt[1][rc[e]] + jt[2][rb[e]] * jt[2][rc[e]]);
-      if (o64) o64[e * stride + idx] = v;
-      if (o32) o32[e * stride + idx] = (float)v;
+      if (o64) o64[e * stride + at] = v;
+      if (o32) o32[e * stride + at] = (float)v;
     }
   } else {
-    if (o64) o64[idx] = cjxw;
-    if (o32) o32[idx] = (float)cjxw;
+    if (o64) o64[at] = cjxw;
+    if (o32) o32[at] = (float)cjxw;
   }
 }
 
@@ -531,12 +534,34 @@ static int geom_kind(const dg_geometry *geom, const dg_coefficient *coef, bool f
   return coef->kind == DG_COEF_SINCOS ? AFFINE_VAR : AFFINE_CONST;
 }
 
+// cells per group of the stored cell geometry layout (kGeoGroup<n>)
+static int geo_group(int n)
+{
+  switch (n) {
+    case 2: return kGeoGroup<2>;
+    case 3: return kGeoGroup<3>;
+    case 4: return kGeoGroup<4>;
+    case 5: return kGeoGroup<5>;
+    case 6: return kGeoGroup<6>;
+    case 7: return kGeoGroup<7>;
+    case 8: return kGeoGroup<8>;
+    default: return kGeoGroup<9>;
+  }
+}
+
+// cells the stored cell geometry arrays hold: ncells rounded up to whole groups
+static int64_t geo_cells(int64_t ncells, int n)
+{
+  const int64_t g = geo_group(n);
+  return (ncells + g - 1) / g * g;
+}
+
 static size_t footprint_bytes(const int64_t nc[3], int n, int gk64, int gk32, unsigned prec)
 {
   const int64_t ncells = nc[0] * nc[1] * nc[2];
   const int64_t n2 = n * n, n3 = n2 * n;
   auto values = [&](int gk) {
-    int64_t vals = geom_cell_values(gk) * ncells * n3;
+    int64_t vals = geom_cell_values(gk) * geo_cells(ncells, n) * n3;
     for (int a = 0; a < 3; ++a) {
       const int64_t nf = ncells / nc[a] * (nc[a] + 1);
       vals += geom_face_values(gk) * nf * n2;
@@ -767,7 +792,7 @@ static dg_status setup_impl(const dg_mesh *mesh, int degree, int basis, const dg
     const size_t es = p == 0 ? 8 : 4;
     const int64_t ncv = geom_cell_values(p == 0 ? op->gk : op->gk32);
     if (ncv) {
-      op->cell_geo[p] = op_alloc(op, ncv * op->ncells * n3 * es);
+      op->cell_geo[p] = op_alloc(op, ncv * geo_cells(op->ncells, op->n) * n3 * es);
       if (!op->cell_geo[p]) return cleanup(fail(DG_ERR_OOM, "cell geometry allocation failed"));
     }
     if (nfv)
@@ -776,20 +801,22 @@ static dg_status setup_impl(const dg_mesh *mesh, int degree, int basis, const dg
         if (!op->face_geo[p][a]) return cleanup(fail(DG_ERR_OOM, "face geometry allocation failed"));
       }
   }
+  const int64_t gstride = geo_cells(op->ncells, op->n) * n3;   // elements per quantity array
   {
     const int64_t npts = op->ncells * n3;
     const int grid = (int)((npts + 255) / 256);
+    const int group = geo_group(op->n);
     auto cells = [&](int gk, double *o64, float *o32) {
       if (!o64 && !o32) return;
-      if (gk == CURVED) hipLaunchKernelGGL(geom_cells_kernel<CURVED>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
+      if (gk == CURVED) hipLaunchKernelGGL(geom_cells_kernel<CURVED>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, gstride, group);
       else if (gk == CURVED_MERGED)
-        hipLaunchKernelGGL(geom_cells_kernel<CURVED_MERGED>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
+        hipLaunchKernelGGL(geom_cells_kernel<CURVED_MERGED>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, gstride, group);
       else if (gk == CURVED_POS)
-        hipLaunchKernelGGL(geom_cells_kernel<CURVED_POS>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
+        hipLaunchKernelGGL(geom_cells_kernel<CURVED_POS>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, gstride, group);
       else if (gk == ADVECTION)
-        hipLaunchKernelGGL(geom_cells_kernel<ADVECTION>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
+        hipLaunchKernelGGL(geom_cells_kernel<ADVECTION>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, gstride, group);
       else if (gk == AFFINE_VAR)
-        hipLaunchKernelGGL(geom_cells_kernel<AFFINE_VAR>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, npts);
+        hipLaunchKernelGGL(geom_cells_kernel<AFFINE_VAR>, dim3(grid), dim3(256), 0, s, g, npts, o64, o32, gstride, group);
     };
     double *o64 = static_cast<double *>(op->cell_geo[0]);
     float *o32 = static_cast<float *>(op->cell_geo[1]);
@@ -816,9 +843,9 @@ static dg_status setup_impl(const dg_mesh *mesh, int degree, int basis, const dg
       if (e != hipSuccess) return cleanup(hip_fail(e, "face geometry kernel"));
     }
   op->v64.g.cell = static_cast<const double *>(op->cell_geo[0]);
-  op->v64.g.cell_stride = op->ncells * n3;
+  op->v64.g.cell_stride = gstride;
   op->v32.g.cell = static_cast<const float *>(op->cell_geo[1]);
-  op->v32.g.cell_stride = op->ncells * n3;
+  op->v32.g.cell_stride = gstride;
   for (int a = 0; a < 3; ++a) {
     op->v64.g.face[a] = static_cast<const double *>(op->face_geo[0][a]);
     op->v32.g.face[a] = static_cast<const float *>(op->face_geo[1][a]);

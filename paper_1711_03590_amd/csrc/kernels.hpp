@@ -223,6 +223,33 @@ struct Blocking {
   static constexpr int SMEM = B * (2 * N3 + WSZ);  // shared memory in Real units
 };
 
+// Layout of the stored cell geometry (every quantity array): cells in groups
+// of G = Blocking<N>::B, the cells of one apply workgroup; within a group,
+// plane k (the N^2 points with i3 = k) of all G cells comes after plane
+// k - 1, so that a workgroup's load of one plane of one quantity is one
+// contiguous run of G N^2 values.  Point q of cell c sits at
+//   ((c / G) N + q / N^2) G N^2 + (c mod G) N^2 + q mod N^2,
+// the arrays are padded to whole groups, and the padding is never read.
+template <int N>
+inline constexpr int kGeoGroup = Blocking<N>::B;
+template <int N>
+inline constexpr int kGeoPlane = kGeoGroup<N> * N * N;   // distance between planes of one cell
+// index of plane 0, point 0 of a cell
+template <int N>
+__host__ __device__ __forceinline__ int64_t geo_base(int64_t cell)
+{
+  constexpr int G = kGeoGroup<N>;
+  const int c = (int)cell;   // cells < 2^31 (at most 2^31 - 1 DoFs)
+  const int g = c / G;
+  return ((int64_t)g * N * G + (c - g * G)) * (N * N);
+}
+// offset of point q of a cell from its geo_base
+template <int N>
+__host__ __device__ __forceinline__ int geo_off(int q)
+{
+  return (q / (N * N)) * kGeoPlane<N> + q % (N * N);
+}
+
 // Workgroups per CU that the LDS footprint allows (160 KiB per CU).  With
 // 256-thread workgroups this is also the number of waves per SIMD, which is
 // passed to the compiler as the occupancy target so that register
@@ -646,7 +673,7 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
   Real gbuf[NB][GV];
   auto load_geometry = [&](int k, Real (&gb)[GV]) {
     if constexpr (GK == CURVED || GK == CURVED_MERGED) {
-      const int64_t ix = (int64_t)cell * N3 + l + k * N2;
+      const int64_t ix = geo_base<N>(cell) + l + k * kGeoPlane<N>;
       const int64_t cs = op.g.cell_stride;
 #pragma unroll
       for (int m = 0; m < GV; ++m) gb[m] = op.g.cell[m * cs + ix];
@@ -690,7 +717,7 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
         for (int m = 0; m < N; ++m) {
           Real f;
           if constexpr (GK == AFFINE_VAR) {
-            f = op.g.cell[(int64_t)cell * N3 + b + m * kStride<N, D>];
+            f = op.g.cell[geo_base<N>(cell) + geo_off<N>(b + m * kStride<N, D>)];
           } else {
             // the line's own direction is D; l holds the other two indices in increasing order
             f = op.c_vol * w1 * w2 * Real(T.gw[m]);
@@ -784,8 +811,9 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
           // by all its threads); with C_d = a_{d+1} x a_{d+2} and
           // det = a_0 . C_0, J^{-T} g = sum_d C_d g_d / det and
           // t_e = c w / det * C_e . (sum_d C_d g_d)
-          const Real *P = op.g.cell + (int64_t)cell * N3;
+          const Real *P = op.g.cell + geo_base<N>(cell);
           const int64_t cs = op.g.cell_stride;
+          constexpr int CP = kGeoPlane<N>;
           const int i1 = l % N, i2 = l / N;
           Real a[3][3];
 #pragma unroll
@@ -795,9 +823,9 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
             Real sx = Real(-0.0), sy = Real(-0.0), sz = Real(-0.0);
 #pragma unroll
             for (int j = 0; j < N; ++j) {
-              sx = fma(d1[j], P[c * cs + j + N * i2 + N2 * k], sx);
-              sy = fma(d2[j], P[c * cs + i1 + N * j + N2 * k], sy);
-              sz = madd(T.Dco[k][j], P[c * cs + l + N2 * j], sz);
+              sx = fma(d1[j], P[c * cs + j + N * i2 + CP * k], sx);
+              sy = fma(d2[j], P[c * cs + i1 + N * j + CP * k], sy);
+              sz = madd(T.Dco[k][j], P[c * cs + l + CP * j], sz);
             }
             a[0][c] = sx;
             a[1][c] = sy;
@@ -812,7 +840,7 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
             C[d][2] = u[0] * v[1] - u[1] * v[0];
           }
           const Real det = a[0][0] * C[0][0] + a[0][1] * C[0][1] + a[0][2] * C[0][2];
-          const Real cw = P[3 * cs + p] * w12 * Real(T.gw[k]) / det;
+          const Real cw = P[3 * cs + l + CP * k] * w12 * Real(T.gw[k]) / det;
           Real v[3];
 #pragma unroll
           for (int c = 0; c < 3; ++c) v[c] = C[0][c] * g[0] + C[1][c] * g[1] + C[2][c] * g[2];
@@ -948,7 +976,7 @@ sipg_diag_kernel(const OpView<double> op, double *__restrict__ d64, float *__res
   if constexpr (GK == CURVED_POS) __syncthreads();  // Dcl is read below
   // effective coefficient at quadrature point q = i
   if (act) {
-    const int64_t ix = (int64_t)cell * N3 + i;
+    const int64_t ix = geo_base<N>(cell) + geo_off<N>(i);
     const int64_t cs = op.g.cell_stride;
     double m[6];
     if constexpr (GK == CURVED) {
@@ -967,7 +995,7 @@ sipg_diag_kernel(const OpView<double> op, double *__restrict__ d64, float *__res
       // the Jacobian's columns by collocation derivatives of the positions,
       // then M = c w det J^{-1} J^{-T} = c w / det C^T C (C_d = a_{d+1} x a_{d+2})
       const int qi[3] = {i % N, (i / N) % N, i / N2};
-      const int64_t c0 = (int64_t)cell * N3;
+      const int64_t c0 = geo_base<N>(cell);
       double a[3][3];
       for (int d = 0; d < 3; ++d)
         for (int c = 0; c < 3; ++c) {
@@ -975,7 +1003,7 @@ sipg_diag_kernel(const OpView<double> op, double *__restrict__ d64, float *__res
           for (int mm = 0; mm < N; ++mm) {
             int r[3] = {qi[0], qi[1], qi[2]};
             r[d] = mm;
-            sum += Dcl[qi[d] * N + mm] * op.g.cell[c * cs + c0 + r[0] + N * r[1] + N2 * r[2]];
+            sum += Dcl[qi[d] * N + mm] * op.g.cell[c * cs + c0 + r[0] + N * r[1] + kGeoPlane<N> * r[2]];
           }
           a[d][c] = sum;
         }

@@ -74,27 +74,36 @@ def test_validation_without_device(dg):
         dg.footprint(2000, 4)   # more than 2^31-1 DoFs
 
 
+def _geo_cells(cells, n):
+    """Cells the stored cell-geometry arrays hold: padded to whole groups of
+    one apply workgroup's cells (128 threads, n^2 per cell)."""
+    g = 128 // (n * n)
+    return -(-cells // g) * g
+
+
 def test_footprint_counts(dg):
     # curved: 10 values per cell point, 4 per face point, plus the diagonal
     k, N = 4, 32
     n = k + 1
     cells = N ** 3
+    gc = _geo_cells(cells, n)
+    assert gc == 32770
     faces = 3 * N * N * (N + 1)
-    vals = 10 * cells * n ** 3 + 4 * faces * n ** 2
+    vals = 10 * gc * n ** 3 + 4 * faces * n ** 2
     assert dg.footprint(N, k, curved=True, precisions=dg.PREC_F64) == vals * 8 + cells * n ** 3 * 8
     assert dg.footprint(N, k, precisions=dg.PREC_F64 | dg.PREC_F32) == cells * n ** 3 * 12
     assert dg.footprint(N, k, variable_coef=True, precisions=dg.PREC_F32) == \
-        (cells * n ** 3 + faces * n ** 2) * 4 + cells * n ** 3 * 4
+        (gc * n ** 3 + faces * n ** 2) * 4 + cells * n ** 3 * 4
 
 
 def test_footprint_merged_geometry(dg):
     # merged (G4): 6 values per cell point instead of 10; faces unchanged
     k, N = 4, 32
     n = k + 1
-    cells = N ** 3
+    gc = _geo_cells(N ** 3, n)
     full = dg.footprint(N, k, curved=True)
     merged = dg.footprint(N, k, curved=True, merged=True)
-    assert full - merged == 4 * cells * n ** 3 * (8 + 4)
+    assert full - merged == 4 * gc * n ** 3 * (8 + 4)
     # the storage choice does not apply to affine maps
     assert dg.footprint(N, k, merged=True) == dg.footprint(N, k)
 
@@ -115,7 +124,7 @@ def test_footprint_advection(dg):
     n = k + 1
     cells = N ** 3
     faces = 3 * N * N * (N + 1)
-    vals = 3 * cells * n ** 3 + faces * n ** 2
+    vals = 3 * _geo_cells(cells, n) * n ** 3 + faces * n ** 2
     assert dg.footprint_advection(N, k, curved=True) == vals * 12
     assert dg.footprint_advection(N, k, velocity=(1.0, 0.0, 0.0), precisions=dg.PREC_F32) == vals * 4
     with pytest.raises(ValueError):
@@ -184,8 +193,9 @@ def test_footprint_mixed_storage(dg):
     n = k + 1
     cells = N ** 3
     faces = 3 * N * N * (N + 1)
-    f64 = (10 * cells * n ** 3 + 4 * faces * n ** 2 + cells * n ** 3) * 8
-    f32 = (6 * cells * n ** 3 + 4 * faces * n ** 2 + cells * n ** 3) * 4
+    gc = _geo_cells(cells, n)
+    f64 = (10 * gc * n ** 3 + 4 * faces * n ** 2 + cells * n ** 3) * 8
+    f32 = (6 * gc * n ** 3 + 4 * faces * n ** 2 + cells * n ** 3) * 4
     assert dg.footprint(N, k, curved=True, storage="mixed") == f64 + f32
     assert dg.footprint(N, k, curved=True, storage="mixed", precisions=dg.PREC_F32) == f32
     with pytest.raises(ValueError):
@@ -198,7 +208,7 @@ def test_footprint_positions_storage(dg):
     n = k + 1
     cells = N ** 3
     faces = 3 * N * N * (N + 1)
-    vals = 4 * cells * n ** 3 + 4 * faces * n ** 2 + cells * n ** 3
+    vals = 4 * _geo_cells(cells, n) * n ** 3 + 4 * faces * n ** 2 + cells * n ** 3
     assert dg.footprint(N, k, curved=True, storage="positions") == vals * 12
 
 
