@@ -249,6 +249,17 @@ __host__ __device__ __forceinline__ int geo_off(int q)
 {
   return (q / (N * N)) * kGeoPlane<N> + q % (N * N);
 }
+// the line of direction D through face point l (the same lines as
+// line_base): offset of its first point from geo_base, and the stride
+template <int N, int D>
+__device__ __forceinline__ int geo_line(int l)
+{
+  if constexpr (D == 2) return l;
+  else if constexpr (D == 1) return (l / N) * kGeoPlane<N> + l % N;
+  else return (l / N) * kGeoPlane<N> + (l % N) * N;
+}
+template <int N, int D>
+inline constexpr int kGeoStride = (D == 0) ? 1 : (D == 1 ? N : kGeoPlane<N>);
 
 // Workgroups per CU that the LDS footprint allows (160 KiB per CU).  With
 // 256-thread workgroups this is also the number of waves per SIMD, which is
@@ -712,12 +723,12 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
         load_line<N, D>(Q, l, v);
         eo_apply<N, M_DCO>(v, g);
         const Real ih2 = op.inv_h[D] * op.inv_h[D];
-        const int b = line_base<N, D>(l);
+        const int64_t gl = geo_base<N>(cell) + geo_line<N, D>(l);
 #pragma unroll
         for (int m = 0; m < N; ++m) {
           Real f;
           if constexpr (GK == AFFINE_VAR) {
-            f = op.g.cell[geo_base<N>(cell) + geo_off<N>(b + m * kStride<N, D>)];
+            f = op.g.cell[gl + m * kGeoStride<N, D>];
           } else {
             // the line's own direction is D; l holds the other two indices in increasing order
             f = op.c_vol * w1 * w2 * Real(T.gw[m]);
