@@ -130,8 +130,10 @@ typedef struct dg_op dg_op; /* opaque, library-owned */
 #define DG_PREC_F64 1u
 #define DG_PREC_F32 2u
 
-/* Bytes of device memory dg_setup will allocate for this problem (geometry,
- * diagonal, solver workspace excluded).  Pure host computation. */
+/* Bytes of device memory dg_setup will allocate for this problem: the stored
+ * cell and face geometry and the Jacobi diagonal of every enabled precision
+ * (solver workspace, which dg_cg_solve and the batch allocate per call or per
+ * request, is not included).  Pure host computation. */
 dg_status dg_footprint(const dg_mesh *mesh, int degree, const dg_geometry *geom,
                        const dg_coefficient *coef, unsigned precisions, size_t *bytes);
 

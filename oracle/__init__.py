@@ -15,6 +15,8 @@ Parity status per function (what pins it is in tests/test_oracle_*.py):
                                 space, SPD, convergence order (curved, variable c)
   block_rows / assemble         pinned through apply (column identity) and the
                                 exact-rational brute force
+  spmv_blocks                   pinned: equals apply on every row, and the
+                                scipy product of the assembled matrix
   diag_cells                    pinned: equals the diagonal of the brute-force matrix
   face_point / volume           pinned: boundary area element, mapped volume
   rhs / errors                  pinned: GLL-weight closed form, convergence order
@@ -39,7 +41,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# DG_ORACLE_LIB selects another build of the same source (the sanitizer build)
+_LIB_PATH = os.environ.get("DG_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 DIRICHLET, NEUMANN = 0, 1
@@ -130,6 +133,7 @@ def lib():
         L.orc_apply_cells.argtypes = [pp, dp, lp, ctypes.c_int64, dp]
         L.orc_diag_cells.argtypes = [pp, lp, ctypes.c_int64, dp]
         L.orc_block_rows.argtypes = [pp, lp, ctypes.c_int64, dp]
+        L.orc_spmv_blocks.argtypes = [pp, lp, ctypes.c_int64, dp, dp, dp]
         L.orc_cell_jacobian.argtypes = [pp, ctypes.c_int64, ctypes.c_int, dp, dp]
         L.orc_face_point.argtypes = [pp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         L.orc_volume.argtypes = [pp, dp]
@@ -234,6 +238,21 @@ def block_rows(p, cells):
     out = np.empty(len(cells) * 7 * n3 * n3)
     _check(lib().orc_block_rows(ctypes.byref(p), _lp(cells), len(cells), _dp(out)), "block_rows")
     return out.reshape(len(cells), 7, n3, n3)
+
+
+def spmv_blocks(p, cells, blocks, src):
+    """Rows of the given cells of A src from their assembled block rows
+    (as block_rows returns them): the matrix-based apply."""
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    blocks = np.ascontiguousarray(blocks, dtype=np.float64)
+    src = np.ascontiguousarray(src, dtype=np.float64)
+    n3 = (p.degree + 1) ** 3
+    if blocks.size != len(cells) * 7 * n3 * n3 or src.size != n_dofs(p):
+        raise ValueError("blocks or src do not match the problem")
+    out = np.empty(len(cells) * n3)
+    _check(lib().orc_spmv_blocks(ctypes.byref(p), _lp(cells), len(cells), _dp(blocks), _dp(src), _dp(out)),
+           "spmv_blocks")
+    return out.reshape(len(cells), n3)
 
 
 def neighbours(p, cell):

@@ -841,6 +841,45 @@ int orc_block_rows(const orc_problem *P, const int64_t *cells, int64_t ncells, d
 /* The cell Jacobian the SIPG cell term uses at Gauss point q of cell e
  * (J[3*i + d] = dx_i/dxi_d; the interpolant's for cellgeo = 1) and the map's
  * own (Jmap, same layout). */
+/* The matrix-based form of y = A u on the rows of the given cells: the
+ * block rows of orc_block_rows (the assembled matrix of Sec. 2 Eq. (3),
+ * seven n^3 x n^3 blocks per cell) multiplied with the source, a plain
+ * block-sparse matrix-vector product with one OpenMP task per block row:
+ *   y_l = B[l][0] u_{cells[l]} + sum_f B[l][1+f] u_{neighbour(cells[l], f)}.
+ * blocks holds ncells * 7 * n^3 * n^3 values as orc_block_rows writes them;
+ * dst receives ncells * n^3 values (the rows of cells[l] at l * n^3). */
+int orc_spmv_blocks(const orc_problem *P, const int64_t *cells, int64_t ncells, const double *blocks,
+                    const double *src, double *dst)
+{
+  orc_ctx c;
+  int rc = ctx_init(&c, P);
+  if (rc) return rc;
+  const int64_t total = (int64_t)P->ncell[0] * P->ncell[1] * P->ncell[2];
+  const int n3 = c.n3;
+  const size_t bs = (size_t)n3 * n3;
+  int err = ORC_OK;
+#pragma omp parallel for schedule(static)
+  for (int64_t l = 0; l < ncells; ++l) {
+    const int64_t e = cells[l];
+    double *y = dst + (size_t)l * n3;
+    if (e < 0 || e >= total) { err = ORC_ERR_ARG; continue; }
+    for (int i = 0; i < n3; ++i) y[i] = 0.0;
+    for (int blk = 0; blk < 7; ++blk) {
+      const int64_t col = blk == 0 ? e : neighbour(&c, e, blk - 1);
+      if (col < 0) continue;
+      const double *B = blocks + ((size_t)l * 7 + (size_t)blk) * bs;
+      const double *u = src + (size_t)col * n3;
+      for (int i = 0; i < n3; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < n3; ++j) s += B[(size_t)i * n3 + j] * u[j];
+        y[i] += s;
+      }
+    }
+  }
+  ctx_free(&c);
+  return err;
+}
+
 int orc_cell_jacobian(const orc_problem *P, int64_t e, int q, double *J, double *Jmap)
 {
   orc_ctx c;

@@ -30,20 +30,6 @@
 
 namespace dgk {
 
-#define DG_EXTERN_N(N)                                                                  \
-  extern template hipError_t launch_apply<N>(const dg_op *, const void *, void *, bool, \
-                                             hipStream_t);                              \
-  extern template hipError_t launch_diag<N>(const dg_op *, void *, void *, hipStream_t);
-DG_EXTERN_N(2)
-DG_EXTERN_N(3)
-DG_EXTERN_N(4)
-DG_EXTERN_N(5)
-DG_EXTERN_N(6)
-DG_EXTERN_N(7)
-DG_EXTERN_N(8)
-DG_EXTERN_N(9)
-#undef DG_EXTERN_N
-
 // threads per workgroup of the batched apply: 128 up to degree 4, 256 above
 // (measured per degree on single requests: 128 threads are 10 % faster at
 // degrees 2 and 4, 256 threads 8 to 23 % faster at degrees 6 and 7)

@@ -127,9 +127,8 @@ dg_status hip_fail(hipError_t e, const char *what);
 void *op_alloc(dg_op *op, size_t bytes);
 void op_free(dg_op *op, void *p);
 
-// kernel launchers (one translation unit per n instantiates them)
-template <int N>
-hipError_t launch_apply(const dg_op *op, const void *src, void *dst, bool f32, hipStream_t s);
+// kernel launchers (one translation unit per n instantiates them; launch_apply
+// and launch_face_traces are declared with their definitions in kernels.hpp)
 template <int N>
 hipError_t launch_diag(const dg_op *op, void *diag64, void *diag32, hipStream_t s);
 

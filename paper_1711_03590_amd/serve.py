@@ -34,7 +34,12 @@ def request_bytes(req):
             + WORKSPACE_BYTES_PER_DOF * n, n)
 
 
-def serve(trace, *, budget_bytes, max_slots=32, rounds_per_step=10, rel_tol=1e-8, time_limit=None, log=None):
+def serve(trace, *, budget_bytes, max_slots=32, rounds_per_step=10, rel_tol=1e-8, time_limit=None, log=None,
+          keep=None):
+    """Serve `trace` (dicts with arrival, ncell, degree, curved, rhs_seed).
+    log(record) is called for every finished request; for requests where
+    keep(request) is true the record also holds host copies of the
+    right-hand side "b" and the solution "x" (for checking them elsewhere)."""
     import torch
     t0 = time.perf_counter()
     pending = collections.deque(sorted(trace, key=lambda r: r["arrival"]))
@@ -42,6 +47,11 @@ def serve(trace, *, budget_bytes, max_slots=32, rounds_per_step=10, rel_tol=1e-8
     inflight = {}
     done = []
     used = peak = 0
+    # device memory actually in use (hipMemGetInfo), relative to the start
+    free0, total = torch.cuda.mem_get_info()
+    dev_peak = 0
+    torch.cuda.reset_peak_memory_stats()
+    alloc0 = torch.cuda.memory_allocated()
     batch = Batch(max_slots)
     try:
         while pending or waiting or inflight:
@@ -72,17 +82,21 @@ def serve(trace, *, budget_bytes, max_slots=32, rounds_per_step=10, rel_tol=1e-8
                                       admitted=time.perf_counter() - t0)
             if inflight:
                 batch.run(rounds_per_step)
+                dev_peak = max(dev_peak, free0 - torch.cuda.mem_get_info()[0])
             elif pending:
                 time.sleep(max(0.0, min(0.002, pending[0]["arrival"] - (time.perf_counter() - t0))))
             for slot, st in batch.poll():
                 rec = inflight.pop(slot)
                 t = time.perf_counter() - t0
+                extra = {}
+                if keep is not None and keep(rec["req"]):
+                    extra = dict(b=rec["b"].cpu().numpy(), x=rec["x"].cpu().numpy())
                 used -= rec["need"]
                 rec["op"].close()
                 done.append(dict(rec["req"], ndofs=rec["ndofs"], admitted=rec["admitted"], completed=t,
                                  latency=t - rec["req"]["arrival"], converged=st["final_rel_residual"] <= rel_tol,
                                  iters=st["iters_inner"], refinements=st["iters_outer"],
-                                 final_rel_residual=st["final_rel_residual"]))
+                                 final_rel_residual=st["final_rel_residual"], **extra))
                 if log:
                     log(done[-1])
     finally:
@@ -100,5 +114,9 @@ def serve(trace, *, budget_bytes, max_slots=32, rounds_per_step=10, rel_tol=1e-8
         "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "mean_dofs": float(np.mean([d["ndofs"] for d in ok])) if ok else 0.0,
         "dofs_solved_per_s": float(np.sum([d["ndofs"] for d in ok]) / elapsed) if ok else 0.0,
-        "peak_hbm_bytes": peak, "budget_bytes": budget_bytes, "max_slots": max_slots,
+        "peak_hbm_bytes": peak, "peak_hbm_bytes_is": "admission ledger (footprints of the resident requests)",
+        "peak_device_bytes_measured": int(dev_peak),
+        "peak_device_bytes_measured_is": "device memory held beyond the start (hipMemGetInfo after each step; includes blocks torch's caching allocator keeps)",
+        "peak_torch_allocated_bytes": int(torch.cuda.max_memory_allocated() - alloc0),
+        "budget_bytes": budget_bytes, "max_slots": max_slots,
     }

@@ -44,3 +44,48 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode != 0
     assert "one MI355X" in (r.stdout + r.stderr)
+
+
+def test_parity_bookkeeping(bench, orc):
+    """keep_rows / check_parity on the host: rows equal to the oracle's give
+    a zero error, perturbed rows an error above the FP64 bar; a kept
+    solution's oracle residual is its true residual."""
+    import numpy as np
+    import torch
+
+    import synth
+    ncell, k = (3, 2, 4), 2
+    p = orc.problem(ncell, k, curved=True)
+    nd = orc.n_dofs(p)
+    seed = 77
+    y = orc.apply(p, synth.src_vector(nd, seed))
+    cells = np.array([0, 5, 23], dtype=np.int64)
+    good, bad = {}, {}
+    bench.keep_rows(good, "f64", torch.from_numpy(y.copy()), cells, (ncell, k, dict(curved=True)), (nd, seed))
+    yb = y.copy()
+    yb[5 * 27 + 3] += 1e-9 * np.abs(y).max()
+    bench.keep_rows(bad, "f64", torch.from_numpy(yb), cells, (ncell, k, dict(curved=True)), (nd, seed))
+    sol = {}
+    x = synth.src_vector(nd, 3)
+    b = orc.apply(p, x)
+    b[0] += 1.0
+    bench.keep_solution(sol, torch.from_numpy(x), torch.from_numpy(b), (ncell, k, dict(curved=True)))
+    bench.check_parity(orc)
+    assert good["err_vs_oracle"]["rel_l2"] == 0.0 and good["err_vs_oracle"]["ok"]
+    assert not bad["err_vs_oracle"]["ok"]
+    assert sol["oracle_rel_residual"]["value"] == pytest.approx(1.0 / np.linalg.norm(b), rel=1e-9)
+    assert not bench.PARITY
+
+
+def test_matrix_baseline_small(bench, orc):
+    """The matrix-based CPU comparator's bookkeeping on a tiny case: the
+    block-sparse product equals the matrix-free apply, and the
+    extrapolation is by the sampled fraction of rows."""
+    import numpy as np
+
+    import synth
+    r = bench.matrix_baseline(orc, np, synth, cases=(("t", 4, 2, dict(curved=True), 16),), spmv_s=0.05)
+    t = r["t"]
+    assert t["rows_assembled"] == 16 and t["of_rows"] == 64 and t["extrapolated_from_sample"]
+    assert t["spmv_vs_matrix_free_rel_l2"] <= 1e-13
+    assert t["matrix_bytes"] == 64 * 7 * 27 * 27 * 8

@@ -1,7 +1,20 @@
-"""Continuous batching (persistent multi-request kernel): every request's
-result is bitwise the same alone and in a mix admitted at different times,
-and agrees with dg_cg_solve's reliable-update mode to the solver
-tolerance; admission limits hold."""
+"""Continuous batching (persistent multi-request kernel) against the oracle.
+
+Every batched request's solution is checked on the same inputs against the
+FP64 oracle: its residual b - A x with the oracle's own operator (Sec. 2,
+Eq. (3), the operator each request's CG replays), and for the small
+requests the solution itself against a direct solve of the oracle's
+assembled matrix.  This holds alone and in a mix admitted at different
+rounds, where each request is also bitwise the same as alone; the batch
+agrees with dg_cg_solve's reliable-update mode to the solver tolerance; the
+served requests of a small trace are re-verified with the oracle; admission
+limits hold.
+
+The requests cover every cell-geometry storage the batch serves (stored
+Jacobians G3, the mixed G3/G4 storage the server uses, the merged G4, the
+positions G2, affine with a constant and with a variable coefficient) and
+every served degree 2..7.
+"""
 import numpy as np
 import pytest
 
@@ -9,11 +22,18 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
+TOL = 1e-10
+# (cells, degree, operator keywords); the oracle problem follows from them
 REQS = [((6, 5, 4), 2, dict(curved=True)),
         ((4, 4, 4), 5, dict(curved=False)),
         ((3, 4, 5), 3, dict(curved=True, variable_coef=True)),
         ((5, 3, 3), 7, dict(curved=True)),
-        ((4, 5, 3), 4, dict(curved=True, merged=True))]
+        ((4, 5, 3), 4, dict(curved=True, merged=True)),
+        ((3, 3, 4), 6, dict(variable_coef=True)),
+        ((4, 3, 4), 3, dict(curved=True, variable_coef=True, storage="mixed")),
+        ((3, 4, 3), 4, dict(curved=True, storage="positions"))]
+# direct solves of the assembled oracle matrix up to this many DoFs
+DIRECT_MAX_DOFS = 8000
 
 
 @pytest.fixture(scope="module")
@@ -23,6 +43,11 @@ def dg():
     assert torch.cuda.is_available()
     dg.lib()
     return dg
+
+
+def _oracle_problem(orc, ncell, k, kw):
+    return orc.problem(ncell, k, curved=kw.get("curved", False), variable_coef=kw.get("variable_coef", False),
+                       cell_geometry="positions" if kw.get("storage") == "positions" else "map")
 
 
 def _make(dg, i):
@@ -38,7 +63,7 @@ def _run_alone(dg, i):
     op, b = _make(dg, i)
     batch = dg.Batch(4)
     x = torch.zeros_like(b)
-    batch.admit(op, b, x, rel_tol=1e-9)
+    batch.admit(op, b, x, rel_tol=TOL)
     out = []
     while batch.active:
         batch.run(7)
@@ -48,11 +73,31 @@ def _run_alone(dg, i):
     return op, b, x, out[0][1]
 
 
-def test_alone_equals_mix_equals_single_solve(dg):
+@pytest.fixture(scope="module")
+def alone(dg):
+    return [_run_alone(dg, i) for i in range(len(REQS))]
+
+
+@pytest.mark.parametrize("i", range(len(REQS)))
+def test_alone_matches_oracle(orc, alone, i):
+    """The batch's solution of request i: residual under the oracle's
+    operator, and the oracle's direct solve for the small requests."""
+    ncell, k, kw = REQS[i]
+    op, b, x, st = alone[i]
+    assert st["final_rel_residual"] <= TOL
+    p = _oracle_problem(orc, ncell, k, kw)
+    bh, xh = b.cpu().numpy(), x.cpu().numpy()
+    res = np.linalg.norm(bh - orc.apply(p, xh)) / np.linalg.norm(bh)
+    assert res <= 2 * TOL, f"request {i}: oracle residual {res:.3e}"
+    if op.n_dofs <= DIRECT_MAX_DOFS:
+        import scipy.sparse.linalg as spla
+        xref = spla.spsolve(orc.assemble_sparse(p).tocsc(), bh)
+        err = np.linalg.norm(xh - xref) / np.linalg.norm(xref)
+        assert err <= 1e-6, f"request {i}: differs from the oracle's direct solve by {err:.3e}"
+
+
+def test_alone_equals_mix_equals_single_solve(dg, orc, alone):
     import torch
-    alone = [_run_alone(dg, i) for i in range(len(REQS))]
-    for op, b, x, st in alone:
-        assert st["final_rel_residual"] <= 1e-9
     # the same requests admitted at different rounds into one batch
     batch = dg.Batch(3)
     mix = {}
@@ -64,23 +109,30 @@ def test_alone_equals_mix_equals_single_solve(dg):
             i = pend.pop(0)
             op, b = _make(dg, i)
             x = torch.zeros_like(b)
-            slot = batch.admit(op, b, x, rel_tol=1e-9)
+            slot = batch.admit(op, b, x, rel_tol=TOL)
             mix[slot] = (i, op, b, x)
         batch.run(3)
         rounds += 3
         for slot, st in batch.poll():
             i, op, b, x = mix.pop(slot)
-            stats[i] = (x, st)
+            stats[i] = (x, b, st)
     batch.close()
     for i in range(len(REQS)):
-        x_mix, st_mix = stats[i]
+        x_mix, b_mix, st_mix = stats[i]
         assert torch.equal(x_mix, alone[i][2]), f"request {i} differs alone vs in the mix"
         assert st_mix["iters_inner"] == alone[i][3]["iters_inner"]
+        # and in the mix too, the oracle's residual (bitwise the same x, but
+        # checked on its own so that the mix is anchored independently)
+        ncell, k, kw = REQS[i]
+        p = _oracle_problem(orc, ncell, k, kw)
+        bh = b_mix.cpu().numpy()
+        res = np.linalg.norm(bh - orc.apply(p, x_mix.cpu().numpy())) / np.linalg.norm(bh)
+        assert res <= 2 * TOL, f"request {i} in the mix: oracle residual {res:.3e}"
     # and the single-request solver in its reliable-update mode: the same
     # method, but its p.(A p) comes out of the apply (workgroup partials in
     # another grouping), so the two agree to the solver tolerance
     for i, (op, b, x, st) in enumerate(alone):
-        xs, sts = op.cg_solve(b, mode=2, rel_tol=1e-9, rel_tol_inner=0.3, check_every=10)
+        xs, sts = op.cg_solve(b, mode=2, rel_tol=TOL, rel_tol_inner=0.3, check_every=10)
         assert sts["converged"]
         assert float(torch.linalg.norm(xs - x) / torch.linalg.norm(x)) <= 1e-6, \
             f"request {i}: batch differs from dg_cg_solve"
@@ -107,14 +159,25 @@ def test_batch_limits(dg):
     batch.close()
 
 
-def test_serve_small_trace(dg):
+def test_serve_small_trace(dg, orc):
+    """The request loop on a small trace: every request completes within the
+    budget, and the three smallest served solutions are re-verified with the
+    oracle's operator (the library's own residual is not trusted)."""
     from paper_1711_03590_amd import serve
     trace = synth.request_trace(24, rate=400.0, seed=7, edge_range=(3, 10))
     budget = 2 * max(serve.request_bytes(r)[0] for r in trace)
+    by_size = sorted(trace, key=lambda r: serve.request_bytes(r)[1])
+    keep_ids = {r["id"] for r in by_size[:3]}
     seen = []
     rep = serve.serve(trace, budget_bytes=budget, max_slots=6, rounds_per_step=5, rel_tol=1e-8,
-                      log=seen.append)
+                      log=seen.append, keep=lambda r: r["id"] in keep_ids)
     assert rep["completed"] == 24 and rep["all_converged"]
     assert rep["peak_hbm_bytes"] <= budget
     assert all(d["latency"] > 0 for d in seen)
     assert np.isfinite(rep["p99_ms"])
+    kept = [d for d in seen if "x" in d]
+    assert len(kept) == 3
+    for d in kept:
+        p = orc.problem(d["ncell"], d["degree"], curved=d["curved"])
+        res = np.linalg.norm(d["b"] - orc.apply(p, d["x"])) / np.linalg.norm(d["b"])
+        assert res <= 2e-8, f"served request {d['id']}: oracle residual {res:.3e}"
