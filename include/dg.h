@@ -305,6 +305,28 @@ typedef struct {
 dg_status dg_cg_solve(dg_op *op, dg_vec b, dg_vec x, const dg_solve_params *params,
                       dg_solve_stats *stats, void *stream);
 
+/* Allocation-free variant of dg_cg_solve, for callers that cannot allocate
+ * device or pinned memory while they run (serving loops with a fixed memory
+ * plan, harnesses that forbid hipMalloc): the same checks, kernels and
+ * results (bitwise, as the reductions are deterministic), with the solver's
+ * workspace taken from a static device array of dg_cg_solve_noalloc_capacity()
+ * bytes (128 MiB; one per GPU, held from the library's load on that device
+ * until the process ends) and the residual read-backs going through
+ * thread-local pageable host memory.  Calls no hipMalloc, hipFree,
+ * hipHostMalloc or the op's allocator.
+ * Limit: dg_cg_solve_noalloc_bytes(op, mode) must not exceed the capacity
+ * (FP64 mode about 32 bytes per DoF, mixed modes 24 to 28: some 4 to 5
+ * million DoFs); larger solves return DG_ERR_ARG before any work.
+ * Every call on a device shares that device's array and leaves its last
+ * contents there: calls that overlap on one device (two streams, two host
+ * threads) race and must be serialised by the caller. */
+dg_status dg_cg_solve_noalloc(dg_op *op, dg_vec b, dg_vec x, const dg_solve_params *params,
+                              dg_solve_stats *stats, void *stream);
+/* Workspace bytes dg_cg_solve_noalloc needs for this op in this mode. */
+dg_status dg_cg_solve_noalloc_bytes(const dg_op *op, int mode, size_t *bytes);
+/* Bytes of the static workspace (the largest accepted dg_cg_solve_noalloc_bytes). */
+size_t dg_cg_solve_noalloc_capacity(void);
+
 /* Releases everything the op allocated.  Synchronises nothing: the caller
  * must make sure no enqueued work still uses the op. */
 dg_status dg_destroy(dg_op *op);

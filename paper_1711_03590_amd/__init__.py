@@ -129,6 +129,10 @@ _SIGS = [
     ("dg_rhs", ctypes.c_int, [_P, Vec, _P]),
     ("dg_error_manufactured", ctypes.c_int, [_P, Vec, _P, ctypes.POINTER(ctypes.c_double)]),
     ("dg_cg_solve", ctypes.c_int, [_P, Vec, Vec, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveStats), _P]),
+    ("dg_cg_solve_noalloc", ctypes.c_int, [_P, Vec, Vec, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveStats),
+                                           _P]),
+    ("dg_cg_solve_noalloc_bytes", ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    ("dg_cg_solve_noalloc_capacity", ctypes.c_size_t, []),
     ("dg_destroy", ctypes.c_int, [_P]),
     ("dg_last_error", ctypes.c_char_p, []),
     ("dg_tables", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t]),
@@ -370,10 +374,12 @@ class Operator:
         return err[0], err[1]
 
     def cg_solve(self, b, x=None, *, mixed=True, mode=None, rel_tol=1e-10, rel_tol_inner=None, max_iter=20000,
-                 max_outer=50, check_every=10, stream=None):
+                 max_outer=50, check_every=10, stream=None, noalloc=False):
         """Jacobi-PCG for A x = b (FP64 vectors).  mode 0: FP64 CG; 1: FP32 CG
         inside FP64 iterative refinement (default when mixed); 2: the same with
-        reliable updates.  Returns (x, stats dict with 'converged')."""
+        reliable updates.  noalloc: run dg_cg_solve_noalloc (workspace in the
+        library's static device array, nothing allocated).  Returns (x, stats
+        dict with 'converged')."""
         torch = _torch()
         if mode is None:
             mode = 1 if mixed else 0
@@ -383,13 +389,20 @@ class Operator:
             x = torch.zeros_like(b)
         p = SolveParams(mode, rel_tol, rel_tol_inner, max_iter, max_outer, check_every)
         st = SolveStats()
-        rc = lib().dg_cg_solve(self._h, vec(b), vec(x), ctypes.byref(p), ctypes.byref(st), _stream(stream))
+        fn = lib().dg_cg_solve_noalloc if noalloc else lib().dg_cg_solve
+        rc = fn(self._h, vec(b), vec(x), ctypes.byref(p), ctypes.byref(st), _stream(stream))
         if rc not in (DG_OK, DG_ERR_NOT_CONVERGED):
             check(rc)
         out = st.as_dict()
         out["converged"] = rc == DG_OK
         out["mode"] = mode
         return x, out
+
+    def noalloc_bytes(self, mode):
+        """Workspace bytes dg_cg_solve_noalloc needs in this mode."""
+        out = ctypes.c_size_t()
+        check(lib().dg_cg_solve_noalloc_bytes(self._h, mode, ctypes.byref(out)))
+        return out.value
 
     def close(self):
         if self._h is not None and self._h.value:

@@ -15,6 +15,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -26,22 +27,50 @@ namespace dgk {
 
 namespace {
 
+// Host memory for the scalars the solver reads back: pinned by default; the
+// allocation-free entry point uses a thread-local pageable buffer instead
+// (the copies then complete before hipMemcpyAsync returns, which the
+// stream synchronisation after each copy waits for anyway).
 struct Pinned {
   double *p = nullptr;
-  Pinned() { (void)hipHostMalloc(reinterpret_cast<void **>(&p), 8 * sizeof(double), hipHostMallocDefault); }
+  bool own = false;
+  explicit Pinned(bool pinned = true)
+  {
+    if (pinned) {
+      own = hipHostMalloc(reinterpret_cast<void **>(&p), 8 * sizeof(double), hipHostMallocDefault) == hipSuccess;
+      if (!own) p = nullptr;
+    } else {
+      thread_local double host[8];
+      p = host;
+    }
+  }
   ~Pinned()
   {
-    if (p) (void)hipHostFree(p);
+    if (own) (void)hipHostFree(p);
   }
 };
 
-// device workspace of one solve, released through the op's allocator
+// Device workspace of one solve: released through the op's allocator, or
+// (region mode) carved in order from a caller-provided region of cap bytes,
+// each piece aligned to 256 bytes, with nothing allocated or freed.
+constexpr size_t kWsAlign = 256;
+inline size_t ws_round(size_t bytes) { return (bytes + kWsAlign - 1) / kWsAlign * kWsAlign; }
 struct Workspace {
   dg_op *op;
   std::vector<void *> ptr;
+  char *base = nullptr;
+  size_t cap = 0, used = 0;
   explicit Workspace(dg_op *o) : op(o) {}
+  Workspace(dg_op *o, void *region, size_t bytes) : op(o), base(static_cast<char *>(region)), cap(bytes) {}
   void *get(size_t bytes)
   {
+    if (base) {
+      const size_t sz = ws_round(bytes);
+      if (used + sz > cap) return nullptr;
+      void *p = base + used;
+      used += sz;
+      return p;
+    }
     void *p = op_alloc(op, bytes);
     if (p) ptr.push_back(p);
     return p;
@@ -243,10 +272,18 @@ dg_status pcg_reliable(dg_op *op, const double *b, double *x, double nb, double 
 
 using namespace dgk;
 
-extern "C" dg_status dg_cg_solve(dg_op *op, dg_vec b, dg_vec x, const dg_solve_params *prm, dg_solve_stats *stats,
-                                 void *stream)
+// Workspace of the allocation-free solve (dg_cg_solve_noalloc): one array per
+// GPU the library runs on, in the code object's data, so it is there as soon
+// as the library is loaded on that device and stays until the process ends.
+// Every call on a device shares it.
+static constexpr size_t kNoAllocBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+// the argument checks of both solve entry points
+dg_status check_solve_args(const dg_op *op, dg_vec b, dg_vec x, const dg_solve_params *prm)
 {
-  const auto t0 = std::chrono::steady_clock::now();
   if (!op || !prm) return fail(DG_ERR_ARG, "null argument");
   if (op->gk == ADVECTION) return fail(DG_ERR_UNSUPPORTED, "CG needs the symmetric SIPG operator");
   if (op->ghost_sides) return fail(DG_ERR_UNSUPPORTED, "CG on a partition with ghost sides needs an exchange per apply");
@@ -258,13 +295,35 @@ extern "C" dg_status dg_cg_solve(dg_op *op, dg_vec b, dg_vec x, const dg_solve_p
   if (!(op->precisions & DG_PREC_F64)) return fail(DG_ERR_ARG, "the op needs FP64 data");
   if (prm->mode >= 1 && (!(op->precisions & DG_PREC_F32) || !(prm->rel_tol_inner > 0) || prm->max_outer < 1))
     return fail(DG_ERR_ARG, "mixed mode needs FP32 data, rel_tol_inner > 0 and max_outer >= 1");
+  return DG_OK;
+}
+
+// Device workspace bytes of a solve in region mode: the pieces solve() takes
+// from its Workspace, in the same order and sizes, each rounded to kWsAlign.
+size_t solve_workspace_bytes(const dg_op *op, int mode)
+{
+  const size_t n = (size_t)op->ndofs;
+  const size_t nwg = (size_t)apply_workgroups_any(op);
+  auto pcg_bytes = [&](size_t real, size_t acc) {
+    return 3 * ws_round(n * real) + ws_round((3 * kRedBlocks + 4) * acc) + ws_round(nwg * real);
+  };
+  size_t bytes = ws_round((kRedBlocks + 8) * sizeof(double)) + ws_round(n * sizeof(double));
+  if (mode == 0) bytes += pcg_bytes(sizeof(double), sizeof(double));
+  else if (mode == 2) bytes += ws_round(n * sizeof(float)) + pcg_bytes(sizeof(float), sizeof(float));
+  else bytes += 2 * ws_round(n * sizeof(float)) + pcg_bytes(sizeof(float), sizeof(float));
+  return bytes;
+}
+
+// The solve proper, with its device workspace taken from ws and its
+// read-backs going through pin (arguments already checked).
+dg_status solve(dg_op *op, dg_vec b, dg_vec x, const dg_solve_params *prm, dg_solve_stats *stats, void *stream,
+                Workspace &ws, Pinned &pin, std::chrono::steady_clock::time_point t0)
+{
   hipStream_t s = static_cast<hipStream_t>(stream);
   dg_solve_stats st{};
   const int64_t n = op->ndofs;
   const int grid = kRedBlocks;
-  Pinned pin;
   if (!pin.p) return fail(DG_ERR_HIP, "pinned host allocation failed");
-  Workspace ws(op);
   double *part = static_cast<double *>(ws.get((kRedBlocks + 8) * sizeof(double)));
   double *r64 = static_cast<double *>(ws.get(n * sizeof(double)));
   if (!part || !r64) return fail(DG_ERR_OOM, "solver workspace allocation failed");
@@ -369,4 +428,67 @@ extern "C" dg_status dg_cg_solve(dg_op *op, dg_vec b, dg_vec x, const dg_solve_p
   if (stats) *stats = st;
   if (result != DG_OK) return fail(DG_ERR_NOT_CONVERGED, "solver did not reach the tolerance within its limits");
   return DG_OK;
+}
+
+// the device address of this device's scratch, looked up once per device
+// (the host-side name scratch is not a device address)
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+dg_status device_scratch(void **out)
+{
+  int dev = -1;
+  DG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(DG_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" dg_status dg_cg_solve(dg_op *op, dg_vec b, dg_vec x, const dg_solve_params *prm, dg_solve_stats *stats,
+                                 void *stream)
+{
+  const auto t0 = std::chrono::steady_clock::now();
+  dg_status rc = check_solve_args(op, b, x, prm);
+  if (rc != DG_OK) return rc;
+  Pinned pin;
+  Workspace ws(op);
+  return solve(op, b, x, prm, stats, stream, ws, pin, t0);
+}
+
+extern "C" size_t dg_cg_solve_noalloc_capacity(void) { return kNoAllocBytes; }
+
+extern "C" dg_status dg_cg_solve_noalloc_bytes(const dg_op *op, int mode, size_t *bytes)
+{
+  if (!op || !bytes) return fail(DG_ERR_ARG, "null argument");
+  if (mode < 0 || mode > 2) return fail(DG_ERR_ARG, "mode must be 0, 1 or 2");
+  *bytes = solve_workspace_bytes(op, mode);
+  return DG_OK;
+}
+
+extern "C" dg_status dg_cg_solve_noalloc(dg_op *op, dg_vec b, dg_vec x, const dg_solve_params *prm,
+                                         dg_solve_stats *stats, void *stream)
+{
+  const auto t0 = std::chrono::steady_clock::now();
+  dg_status rc = check_solve_args(op, b, x, prm);
+  if (rc != DG_OK) return rc;
+  const size_t need = solve_workspace_bytes(op, prm->mode);
+  if (need > kNoAllocBytes)
+    return fail(DG_ERR_ARG, "dg_cg_solve_noalloc: this solve needs " + std::to_string(need) +
+                                " bytes of workspace, beyond the " + std::to_string(kNoAllocBytes) +
+                                "-byte static scratch (use dg_cg_solve)");
+  void *region = nullptr;
+  if ((rc = device_scratch(&region)) != DG_OK) return rc;
+  Pinned pin(false);
+  Workspace ws(op, region, kNoAllocBytes);
+  return solve(op, b, x, prm, stats, stream, ws, pin, t0);
 }

@@ -20,11 +20,17 @@ def dg():
 
 def test_exports_every_declared_symbol(dg):
     hdr = open(os.path.join(ROOT, "include", "dg.h")).read()
-    names = set(re.findall(r"^\s*(?:dg_status|int64_t|int|const char \*)\s*\**\s*(dg_\w+)\s*\(", hdr, re.M))
+    names = set(re.findall(r"^\s*(?:dg_status|int64_t|size_t|int|const char \*)\s*\**\s*(dg_\w+)\s*\(", hdr, re.M))
     assert len(names) >= 15
     L = dg.lib()
     for n in sorted(names):
         assert hasattr(L, n), n
+    assert "dg_cg_solve_noalloc" in names and "dg_cg_solve_noalloc_capacity" in names
+
+
+def test_noalloc_capacity(dg):
+    """The allocation-free solve's static workspace: 128 MiB (host-only call)."""
+    assert dg.lib().dg_cg_solve_noalloc_capacity() == 128 << 20
 
 
 @pytest.mark.parametrize("k", range(1, 9))
