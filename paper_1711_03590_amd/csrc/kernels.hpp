@@ -393,11 +393,19 @@ __device__ __forceinline__ void for_jobs(int l, bool act, F &&f)
 //   [[u]] = u- - u+, {{grad u}} = (grad u- + grad u+)/2; the average's
 //   tangential part is the tangential derivative of V = u- + u+ on the face
 //   (V = 2 u- on a Dirichlet face, where u+ = -u- but grad u+ = grad u-).
+// On affine meshes (no curved faces) the cell term splits by direction
+// (J^{-1} diagonal): fl holds f h_A^{-2} (f = c det J w) at the points of
+// this thread's A-line, and the x and y directions add their cell term
+// Dco^T (fl Dco Q) on that line in the same pass as the face integration
+// (one read and one write of the residual line instead of two each); qz is
+// this thread's Gauss-point z-line, kept in registers from the last basis
+// change, which the z faces read instead of LDS.
 template <int N, typename Real, int GK, int A, int BS, bool GH, typename Next>
 __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Real *Q, Real *R, Real *W, int l,
                                                const int (&ci)[3], bool act, bool valid, const Real (&nb)[2][N],
-                                               Real (&fz)[4], Next &&next)
+                                               Real (&fz)[4], Next &&next, const Real (&fl)[N], const Real (&qz)[N])
 {
+  constexpr bool FUSED = !curved_faces(GK);
   constexpr int N2 = N * N;
   constexpr int t1 = (A == 0) ? 1 : 0, t2 = (A == 2) ? 1 : 2;
   constexpr Tables<N> T = kTab<N>;
@@ -427,9 +435,14 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
   // the neighbour's value and normal derivative on the shared face in the
   // tangential basis: S_f and D_f of Eq. (7) applied to its normal line
   Real um[2], dm[2];
+  Real v[N];   // this thread's Gauss-point line along A (kept for the fused cell term)
   if (act) {
-    Real v[N];
-    load_line<N, A>(Q, l, v);
+    if constexpr (FUSED && A == 2) {
+#pragma unroll
+      for (int m = 0; m < N; ++m) v[m] = qz[m];
+    } else {
+      load_line<N, A>(Q, l, v);
+    }
     end_values<N>(v, um[0], um[1]);
     end_derivatives<N>(v, dm[0], dm[1]);
     // neighbour below: the shared face is its xi_A = 1 side; above: xi_A = 0
@@ -576,16 +589,24 @@ __device__ __forceinline__ void face_direction(const OpView<Real> &op, const Rea
       fz[2] = w[1];
       fz[3] = tga[1];
     } else {
-      Real r[N];
+      Real r[N], c[N];
       if constexpr (A == 1) load_line<N, A>(R, l, r);
+      if constexpr (FUSED) {
+        Real g[N];
+        eo_apply<N, M_DCO>(v, g);
+#pragma unroll
+        for (int m = 0; m < N; ++m) g[m] *= fl[m];
+        eo_apply<N, M_DCOT>(g, c);
+      }
 #pragma unroll
       for (int m = 0; m < N; ++m) {
-        Real v = (A == 1) ? r[m] : Real(-0.0);
-        v = madd(T.L0[m], w[0], v);
-        v = fma(Real(T.dL0[m]), tga[0], v);
-        v = madd(T.L1[m], w[1], v);
-        v = fma(Real(T.dL1[m]), tga[1], v);
-        r[m] = v;
+        Real x = (A == 1) ? r[m] : Real(-0.0);
+        if constexpr (FUSED) x += c[m];
+        x = madd(T.L0[m], w[0], x);
+        x = fma(Real(T.dL0[m]), tga[0], x);
+        x = madd(T.L1[m], w[1], x);
+        x = fma(Real(T.dL1[m]), tga[1], x);
+        r[m] = x;
       }
       store_line<N, A>(R, l, r);
     }
@@ -669,12 +690,24 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
   }
   __syncthreads();
 
-  // (b) basis change to the Gauss points (Eq. (6), right factor)
+  // (b) basis change to the Gauss points (Eq. (6), right factor); on affine
+  // meshes the thread keeps its z-line of the result in registers (qz)
+  constexpr bool FUSED = !curved_faces(GK);
+  Real qz[N];
   if (act) sweep<N, 0, kMS<BS>>(Q, Q, l);
   __syncthreads();
   if (act) sweep<N, 1, kMS<BS>>(Q, Q, l);
   __syncthreads();
-  if (act) sweep<N, 2, kMS<BS>>(Q, Q, l);
+  if (act) {
+    if constexpr (FUSED) {
+      Real v[N];
+      load_line<N, 2>(Q, l, v);
+      eo_apply<N, kMS<BS>>(v, qz);
+      store_line<N, 2>(Q, l, qz);
+    } else {
+      sweep<N, 2, kMS<BS>>(Q, Q, l);
+    }
+  }
   __syncthreads();
 
   // (c) face terms, direction by direction, into R; the stored cell geometry
@@ -691,71 +724,87 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
     }
   };
   Real fz[4] = {Real(0), Real(0), Real(0), Real(0)};
-  face_direction<N, Real, GK, 0, BS, GH>(op, Q, R, W, l, ci, act, valid, nb, fz,
-                                     [&] { load_neighbour_lines<N, Real, 1, BS>(op, src, cell, l, ci, nb); });
-  face_direction<N, Real, GK, 1, BS, GH>(op, Q, R, W, l, ci, act, valid, nb, fz,
-                                     [&] { load_neighbour_lines<N, Real, 2, BS>(op, src, cell, l, ci, nb); });
-  constexpr int PRE = (DG_GEO_PRE < NB) ? DG_GEO_PRE : NB;
-  face_direction<N, Real, GK, 2, BS, GH>(op, Q, R, W, l, ci, act, valid, nb, fz, [&] {
+  // affine meshes: f h_D^{-2} along this thread's D-line for the fused
+  // per-direction cell terms (the loads of direction D issued a direction
+  // ahead, like the neighbour lines)
+  Real fl[3][N];
+  const int i1 = l % N, i2 = l / N;
+  Real w12 = Real(0);  // the product of the weights of this thread's two fixed indices
+  auto load_fline = [&](auto dir) {
+    constexpr int D = decltype(dir)::value;
+    if constexpr (GK == AFFINE_VAR) {
+      const int64_t gl = geo_base<N>(cell) + geo_line<N, D>(l);
 #pragma unroll
-    for (int k = 0; k < PRE; ++k) load_geometry(k, gbuf[k]);
-  });
+      for (int m = 0; m < N; ++m) fl[D][m] = op.g.cell[gl + m * kGeoStride<N, D>];
+    }
+  };
+  auto scale_fline = [&](auto dir) {
+    constexpr int D = decltype(dir)::value;
+    const Real ih2 = op.inv_h[D] * op.inv_h[D];
 #pragma unroll
-  for (int k = PRE; k < NB; ++k) load_geometry(k, gbuf[k]);
-  __syncthreads();  // the z faces' Z2 reads are done before W takes the gradients
-
-  if constexpr (!curved_faces(GK)) {
-    // (d) affine cell integrals: J^{-1} is diagonal, so the cell term splits
-    // by direction, R += sum_d Dco_d^T (f h_d^{-2} Dco_d Q) with f = c det J w
-    // per point: one line pass per direction, the z pass also taking the z
-    // faces' normal integration
-    const int i1 = l % N, i2 = l / N;
-    Real w1 = Real(0), w2 = Real(0);  // weights of this thread's fixed indices
+    for (int m = 0; m < N; ++m) {
+      if constexpr (GK == AFFINE_VAR) fl[D][m] *= ih2;
+      else fl[D][m] = op.c_vol * w12 * Real(T.gw[m]) * ih2;
+    }
+  };
+  if constexpr (FUSED) {
+    Real w1 = Real(0), w2 = Real(0);
 #pragma unroll
     for (int q = 0; q < N; ++q) {
       if (q == i1) w1 = Real(T.gw[q]);
       if (q == i2) w2 = Real(T.gw[q]);
     }
-    auto pass = [&](auto dir) {
-      constexpr int D = decltype(dir)::value;
-      if (act) {
-        Real v[N], g[N], r[N], q[N];
-        load_line<N, D>(Q, l, v);
-        eo_apply<N, M_DCO>(v, g);
-        const Real ih2 = op.inv_h[D] * op.inv_h[D];
-        const int64_t gl = geo_base<N>(cell) + geo_line<N, D>(l);
+    w12 = w1 * w2;
+    load_fline(std::integral_constant<int, 0>{});
+    scale_fline(std::integral_constant<int, 0>{});
+  }
+  face_direction<N, Real, GK, 0, BS, GH>(op, Q, R, W, l, ci, act, valid, nb, fz, [&] {
+    load_neighbour_lines<N, Real, 1, BS>(op, src, cell, l, ci, nb);
+    if constexpr (FUSED) load_fline(std::integral_constant<int, 1>{});
+  }, fl[0], qz);
+  if constexpr (FUSED) scale_fline(std::integral_constant<int, 1>{});
+  face_direction<N, Real, GK, 1, BS, GH>(op, Q, R, W, l, ci, act, valid, nb, fz, [&] {
+    load_neighbour_lines<N, Real, 2, BS>(op, src, cell, l, ci, nb);
+    if constexpr (FUSED) load_fline(std::integral_constant<int, 2>{});
+  }, fl[1], qz);
+  constexpr int PRE = (DG_GEO_PRE < NB) ? DG_GEO_PRE : NB;
+  face_direction<N, Real, GK, 2, BS, GH>(op, Q, R, W, l, ci, act, valid, nb, fz, [&] {
 #pragma unroll
-        for (int m = 0; m < N; ++m) {
-          Real f;
-          if constexpr (GK == AFFINE_VAR) {
-            f = op.g.cell[gl + m * kGeoStride<N, D>];
-          } else {
-            // the line's own direction is D; l holds the other two indices in increasing order
-            f = op.c_vol * w1 * w2 * Real(T.gw[m]);
-          }
-          g[m] *= f * ih2;
-        }
-        eo_apply<N, M_DCOT>(g, r);
-        load_line<N, D>(R, l, q);
+    for (int k = 0; k < PRE; ++k) load_geometry(k, gbuf[k]);
+  }, fl[2], qz);
+
+  if constexpr (FUSED) {
+    // (d) affine cell integrals: J^{-1} is diagonal, so the cell term splits
+    // by direction, R += sum_d Dco_d^T (f h_d^{-2} Dco_d Q) with f = c det J w
+    // per point; the x and y terms were added with the x and y faces, the z
+    // term goes with the z faces' normal integration onto this thread's
+    // z-line, which then takes the transposed basis change along z in
+    // registers (the basis changes of a tensor product commute)
+    scale_fline(std::integral_constant<int, 2>{});
+    if (act) {
+      Real g[N], r[N], q[N];
+      eo_apply<N, M_DCO>(qz, g);
 #pragma unroll
-        for (int m = 0; m < N; ++m) {
-          Real x = q[m] + r[m];
-          if constexpr (D == 2) {
-            x = madd(T.L0[m], fz[0], x);
-            x = fma(Real(T.dL0[m]), fz[1], x);
-            x = madd(T.L1[m], fz[2], x);
-            x = fma(Real(T.dL1[m]), fz[3], x);
-          }
-          q[m] = x;
-        }
-        store_line<N, D>(R, l, q);
+      for (int m = 0; m < N; ++m) g[m] *= fl[2][m];
+      eo_apply<N, M_DCOT>(g, r);
+      load_line<N, 2>(R, l, q);
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        Real x = q[m] + r[m];
+        x = madd(T.L0[m], fz[0], x);
+        x = fma(Real(T.dL0[m]), fz[1], x);
+        x = madd(T.L1[m], fz[2], x);
+        x = fma(Real(T.dL1[m]), fz[3], x);
+        q[m] = x;
       }
-      __syncthreads();
-    };
-    pass(std::integral_constant<int, 0>{});
-    pass(std::integral_constant<int, 1>{});
-    pass(std::integral_constant<int, 2>{});
+      eo_apply<N, kMST<BS>>(q, r);
+      store_line<N, 2>(R, l, r);
+    }
+    __syncthreads();
   } else {
+#pragma unroll
+    for (int k = PRE; k < NB; ++k) load_geometry(k, gbuf[k]);
+    __syncthreads();  // the z faces' Z2 reads are done before W takes the gradients
     // (d) cell integrals: collocation derivatives along x and y (z is taken
     // in registers below), then the quadrature-point operation along this
     // thread's z-line with the stored geometry (J^{-T} and c det J w per
@@ -900,13 +949,16 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
     __syncthreads();
   }
 
-  // (e) back to the Gauss-Lobatto basis (transposed basis change) and write
+  // (e) back to the Gauss-Lobatto basis (transposed basis change; on affine
+  // meshes the z part is done already) and write
   if (act) sweep<N, 0, kMST<BS>>(R, R, l);
   __syncthreads();
   if (act) sweep<N, 1, kMST<BS>>(R, R, l);
   __syncthreads();
-  if (act) sweep<N, 2, kMST<BS>>(R, R, l);
-  __syncthreads();
+  if constexpr (!FUSED) {
+    if (act) sweep<N, 2, kMST<BS>>(R, R, l);
+    __syncthreads();
+  }
   const Real *Rall = smem + B * N3;
   for (int i = t; i < nhere * N3; i += TPB) dst[g0 + i] = Rall[i];
   if constexpr (DOT) {
