@@ -156,6 +156,9 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                                "(there is no non-HIP fallback)")
+        # torch first: its HIP runtime is then the one the library binds to
+        # (loaded the other way round, the process would hold two runtimes)
+        _torch()
         L = ctypes.CDLL(LIB_PATH)
         for name, res, args in _SIGS:
             fn = getattr(L, name)

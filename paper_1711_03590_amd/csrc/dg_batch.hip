@@ -213,6 +213,7 @@ struct dg_batch {
   int round = 0;
   bool dirty = true;
   std::vector<int> active;   // request index per descriptor position (ordered by degree)
+  std::vector<int> refreshing;   // descriptor positions taking a refinement step this round
   int nitems = 0;
   // per number of points n: descriptors [slot0[n], ...) and items [item0[n], item1[n])
   int slot0[kBatchMaxN + 1] = {}, item0[kBatchMaxN + 1] = {}, item1[kBatchMaxN + 1] = {};
@@ -249,6 +250,23 @@ dg_status read_scalar(dg_batch *b, const double *dev, double *out, hipStream_t s
   DG_HIP(hipStreamSynchronize(s));
   *out = *b->h_scalar;
   return DG_OK;
+}
+
+// Enqueue the FP64 residual of request r and the copy of its squared norm
+// into host slot *host (pinned); the caller synchronises the stream once for
+// all the requests it refreshes, then calls refresh_done.
+dg_status refresh_async(Request &r, double *host, hipStream_t s)
+{
+  double *dscal = r.dpart + kRedBlocks;
+  DG_HIP(rel_residual_async(r.op, r.b, r.x, r.r64, r.dpart, dscal, r.r, r.nb, s));
+  DG_HIP(hipMemcpyAsync(host, dscal, sizeof(double), hipMemcpyDeviceToHost, s));
+  return DG_OK;
+}
+
+void refresh_done(Request &r, double norm2)
+{
+  r.rel = std::sqrt(norm2) / r.nb;
+  r.st.applies_f64 += 1;
 }
 
 // FP64 residual of request r; stores the relative norm in r.rel
@@ -328,13 +346,15 @@ dg_status dg_batch_create(int max_slots, const dg_allocator *alloc, dg_batch **o
     b->own_alloc = false;
   }
   b->req.resize(max_slots);
+  b->refreshing.resize(max_slots);
   bool ok = hipMalloc(reinterpret_cast<void **>(&b->d_desc), sizeof(BatchSlot) * max_slots) == hipSuccess &&
             hipMalloc(reinterpret_cast<void **>(&b->d_rr), sizeof(float) * max_slots) == hipSuccess &&
             hipHostMalloc(reinterpret_cast<void **>(&b->h_desc), sizeof(BatchSlot) * max_slots,
                           hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc(reinterpret_cast<void **>(&b->h_rr), sizeof(float) * max_slots, hipHostMallocDefault) ==
                 hipSuccess &&
-            hipHostMalloc(reinterpret_cast<void **>(&b->h_scalar), sizeof(double) * 2, hipHostMallocDefault) ==
+            hipHostMalloc(reinterpret_cast<void **>(&b->h_scalar), sizeof(double) * (max_slots + 2),
+                          hipHostMallocDefault) ==
                 hipSuccess;
   if (!ok) {
     dg_batch_destroy(b);
@@ -487,6 +507,11 @@ dg_status dg_batch_run(dg_batch *b, int max_rounds, void *stream)
     hipLaunchKernelGGL(batch_gather_rr_kernel, dim3((na + 63) / 64), dim3(64), 0, s, b->d_desc, na, b->d_rr);
     DG_HIP(hipMemcpyAsync(b->h_rr, b->d_rr, sizeof(float) * na, hipMemcpyDeviceToHost, s));
     DG_HIP(hipStreamSynchronize(s));
+    // refinement steps of every request that reached one: all their FP64
+    // residuals are enqueued first and read back with one synchronisation
+    // (each request's own kernels keep their order, so its result does not
+    // depend on the others)
+    int nref = 0;
     for (int k = 0; k < na; ++k) {
       Request &r = b->req[b->active[k]];
       if (!(r.it % r.prm.check_every == 0 || r.it == r.prm.max_iter)) continue;
@@ -497,23 +522,31 @@ dg_status dg_batch_run(dg_batch *b, int max_rounds, void *stream)
         continue;
       }
       if (r32 <= r.prm.rel_tol || r32 < r.prm.rel_tol_inner * r.rlast || r.it == r.prm.max_iter) {
-        const int64_t n = r.op->ndofs;
-        DG_HIP(flush_correction_async(n, r.x, r.nb, r.e, s));
-        if ((st = refresh(b, r, s)) != DG_OK) return st;
-        if (r.rel <= r.prm.rel_tol) {
-          finish(r, DG_OK);
-          b->dirty = true;
-          continue;
-        }
-        if (r.it >= r.prm.max_iter) {
-          finish(r, DG_ERR_NOT_CONVERGED);
-          b->dirty = true;
-          continue;
-        }
-        r.st.iters_outer += 1;
-        r.rlast = r.rel;
-        DG_HIP(restart_rz_async(n, r.r, static_cast<const float *>(r.op->diag[1]), r.part, (r.it + 1) & 1, s));
+        DG_HIP(flush_correction_async(r.op->ndofs, r.x, r.nb, r.e, s));
+        if ((st = refresh_async(r, b->h_scalar + 2 + k, s)) != DG_OK) return st;
+        b->refreshing[nref++] = k;
       }
+    }
+    if (nref == 0) continue;
+    DG_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < nref; ++j) {
+      const int k = b->refreshing[j];
+      Request &r = b->req[b->active[k]];
+      refresh_done(r, b->h_scalar[2 + k]);
+      if (r.rel <= r.prm.rel_tol) {
+        finish(r, DG_OK);
+        b->dirty = true;
+        continue;
+      }
+      if (r.it >= r.prm.max_iter) {
+        finish(r, DG_ERR_NOT_CONVERGED);
+        b->dirty = true;
+        continue;
+      }
+      r.st.iters_outer += 1;
+      r.rlast = r.rel;
+      DG_HIP(restart_rz_async(r.op->ndofs, r.r, static_cast<const float *>(r.op->diag[1]), r.part, (r.it + 1) & 1,
+                              s));
     }
   }
   DG_HIP(hipStreamSynchronize(s));
