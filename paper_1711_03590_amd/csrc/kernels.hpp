@@ -39,6 +39,7 @@
 #include <type_traits>
 
 #include "dg_internal.hpp"
+#include "reduce.hpp"
 #include "tables.hpp"
 
 namespace dgk {
@@ -621,22 +622,11 @@ struct DotOut {
   Real *part = nullptr;
 };
 
-// fixed-order tree sum over the TPB threads of a workgroup (sh: TPB values)
+// fixed-order sum over the TPB threads of a workgroup (sh: TPB / 64 values)
 template <int TPB, typename Real>
 __device__ __forceinline__ Real wg_sum(Real v, Real *sh)
 {
-  static_assert((TPB & (TPB - 1)) == 0, "power-of-two workgroups");
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-#pragma unroll
-  for (int w = TPB / 2; w > 0; w >>= 1) {
-    if (t < w) sh[t] += sh[t + w];
-    __syncthreads();
-  }
-  const Real r = sh[0];
-  __syncthreads();
-  return r;
+  return workgroup_sum<TPB>(v, sh);
 }
 
 // The fused pass over the cells of one batch (cells blk*B .. blk*B+B-1) by
@@ -927,16 +917,8 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
       store_line<N, 2>(R, l, q);
     }
     __syncthreads();
-    if (act) {
-      Real v[N], r[N], q[N];
-      load_line<N, 0>(G0, l, v);
-      eo_apply<N, M_DCOT>(v, r);
-      load_line<N, 0>(R, l, q);
-#pragma unroll
-      for (int m = 0; m < N; ++m) q[m] += r[m];
-      store_line<N, 0>(R, l, q);
-    }
-    __syncthreads();
+    // the y part first, so that the x-line pass, the last to add to R, can
+    // take the transposed basis change along x before its one store
     if (act) {
       Real v[N], r[N], q[N];
       load_line<N, 1>(G1, l, v);
@@ -947,14 +929,41 @@ __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *
       store_line<N, 1>(R, l, q);
     }
     __syncthreads();
+    if (act) {
+      Real v[N], r[N], q[N];
+      load_line<N, 0>(G0, l, v);
+      eo_apply<N, M_DCOT>(v, r);
+      load_line<N, 0>(R, l, q);
+#pragma unroll
+      for (int m = 0; m < N; ++m) q[m] += r[m];
+      eo_apply<N, kMST<BS>>(q, r);
+      store_line<N, 0>(R, l, r);
+    }
+    __syncthreads();
   }
 
   // (e) back to the Gauss-Lobatto basis (transposed basis change; on affine
-  // meshes the z part is done already) and write
-  if (act) sweep<N, 0, kMST<BS>>(R, R, l);
-  __syncthreads();
+  // meshes z is done already, on curved ones x) and write
+  if constexpr (FUSED) {
+    if (act) sweep<N, 0, kMST<BS>>(R, R, l);
+    __syncthreads();
+  }
   if (act) sweep<N, 1, kMST<BS>>(R, R, l);
   __syncthreads();
+  if constexpr (!FUSED && !DOT) {
+    // the last direction (z) in registers, written straight to dst: the
+    // z-lines of a cell are its N^2 consecutive points per plane, so each
+    // store of a wave covers contiguous runs of its cells' blocks
+    if (valid) {
+      Real v[N], r[N];
+      load_line<N, 2>(R, l, v);
+      eo_apply<N, kMST<BS>>(v, r);
+      Real *out = dst + (int64_t)cell * N3 + l;
+#pragma unroll
+      for (int m = 0; m < N; ++m) out[m * N2] = r[m];
+    }
+    return;
+  }
   if constexpr (!FUSED) {
     if (act) sweep<N, 2, kMST<BS>>(R, R, l);
     __syncthreads();

@@ -6,25 +6,19 @@
 
 #include <cstdint>
 
+#include "reduce.hpp"
+
 namespace dgk {
 
 constexpr int kRedBlocks = 512;   // fixed partition of every reduction
 constexpr int kRedThreads = 256;
 
-// sum over the block in a fixed tree order; every thread gets the result
+// sum over the block in a fixed order (butterfly per wave, then the waves
+// in order); every thread gets the result
 template <typename Acc>
 __device__ __forceinline__ Acc block_sum(Acc v, Acc *sh)
 {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-    if (t < w) sh[t] += sh[t + w];
-    __syncthreads();
-  }
-  const Acc r = sh[0];
-  __syncthreads();
-  return r;
+  return workgroup_sum<kRedThreads>(v, sh);
 }
 
 // the kRedBlocks partials of one reduction, summed in a fixed order
@@ -90,7 +84,7 @@ __global__ void __launch_bounds__(kRedThreads) finalize_kernel(const Acc *__rest
 
 // out[0] = the sum of part[0 .. count) in a fixed order: thread t sums the
 // entries t, t + T, t + 2T, ... (eight loads issued before their adds), then
-// a fixed tree over the T = 1024 threads of the one workgroup
+// the fixed-order workgroup sum over the T = 1024 threads of the one workgroup
 constexpr int kSumThreads = 1024;
 template <typename Acc>
 __device__ __forceinline__ void sum_shares_body(const Acc *__restrict__ part, int count, Acc *out, Acc *sh)
@@ -106,13 +100,8 @@ __device__ __forceinline__ void sum_shares_body(const Acc *__restrict__ part, in
     for (int u = 0; u < 8; ++u) v += a[u];
   }
   for (; i < count; i += kSumThreads) v += part[i];
-  sh[t] = v;
-  __syncthreads();
-  for (int w = kSumThreads / 2; w > 0; w >>= 1) {
-    if (t < w) sh[t] += sh[t + w];
-    __syncthreads();
-  }
-  if (t == 0) out[0] = sh[0];
+  v = workgroup_sum<kSumThreads>(v, sh);
+  if (t == 0) out[0] = v;
 }
 
 template <typename Acc>
