@@ -211,8 +211,21 @@ __device__ __forceinline__ int xcd_remap(int b, int G)
 #ifndef DG_WG_WAVES
 #define DG_WG_WAVES 2
 #endif
+// Threads per workgroup: DG_WG_WAVES waves (more when one cell's N^2 lines
+// need them), or a single wave where that keeps the same share of the lanes
+// busy (N = 2, 3, 4, 7, 8: whole cells fill one wave as well as two), which
+// measures 2-6 % faster there; at N = 5 and 6 one wave would idle a quarter
+// and more of its lanes.
 template <int N>
-inline constexpr int kTpb = (64 * DG_WG_WAVES >= N * N) ? 64 * DG_WG_WAVES : ((N * N + 63) / 64) * 64;
+constexpr int pick_tpb()
+{
+  constexpr int n2 = N * N;
+  constexpr int base = (64 * DG_WG_WAVES >= n2) ? 64 * DG_WG_WAVES : ((n2 + 63) / 64) * 64;
+  if (n2 <= 64 && base > 64 && (64 / n2) * n2 * base == (base / n2) * n2 * 64) return 64;
+  return base;
+}
+template <int N>
+inline constexpr int kTpb = pick_tpb<N>();
 
 template <int N, int TPB_ = kTpb<N>>
 struct Blocking {
