@@ -30,24 +30,31 @@
 
 namespace dgk {
 
-// threads per workgroup of the batched apply: 128 up to degree 4, 256 above
-// (measured per degree on single requests: 128 threads are 10 % faster at
-// degrees 2 and 4, 256 threads 8 to 23 % faster at degrees 6 and 7)
-#ifndef DG_BATCH_TPB_LO
-#define DG_BATCH_TPB_LO 128
-#endif
-#ifndef DG_BATCH_TPB
-#define DG_BATCH_TPB 256
-#endif
+// threads per workgroup of the batched apply: the stand-alone apply's
+// (one wave at 3, 4, 7 and 8 points, two at 5 and 6)
 template <int N>
-constexpr int kBatchTpb = N <= 5 ? DG_BATCH_TPB_LO : DG_BATCH_TPB;
-// the same on the host, for a runtime number of points n
-inline int batch_tpb(int n) { return n <= 5 ? DG_BATCH_TPB_LO : DG_BATCH_TPB; }
+constexpr int kBatchTpb = kTpb<N>;
 // degrees served by the persistent kernel: 2..7 (3..8 points per direction)
 constexpr int kBatchMinN = 3, kBatchMaxN = 8;
-// workgroups of the persistent apply launch (a multiple of kXcds)
+// the same on the host, for a runtime number of points n
+inline int batch_tpb(int n)
+{
+  switch (n) {
+    case 3: return kBatchTpb<3>;
+    case 4: return kBatchTpb<4>;
+    case 5: return kBatchTpb<5>;
+    case 6: return kBatchTpb<6>;
+    case 7: return kBatchTpb<7>;
+    default: return kBatchTpb<8>;
+  }
+}
+// workgroups of the persistent apply launch (a multiple of kXcds): enough
+// one-wave workgroups to hold every wave slot the kernels' register use
+// leaves (3 or 4 per SIMD); on the serving trace this serves 5-7 % more
+// solves per second than 2,048 workgroups of 128 and 256 threads did (a
+// grid of one workgroup per item, not persistent, measures about the same)
 #ifndef DG_BATCH_GRID
-#define DG_BATCH_GRID 2048
+#define DG_BATCH_GRID 12288
 #endif
 constexpr int kXcds = 8;   // XCDs of an MI355X
 static_assert(DG_BATCH_GRID % kXcds == 0, "the persistent grid is a multiple of the XCD count");
