@@ -73,10 +73,17 @@ constexpr int batch_lds()
 }
 template <int N>
 constexpr int kBatchLds = batch_lds<N>();
-// occupancy target (waves per SIMD, i.e. workgroups per CU) given to the
-// compiler: degrees 5 to 7 need more registers than 4 waves leave
-template <int N>
-constexpr int kBatchWaves = N >= 6 ? DG_BATCH_WAVES_HI : DG_BATCH_WAVES;
+// occupancy target (waves per SIMD) given to the compiler: the stand-alone
+// apply's, at most DG_BATCH_WAVES (DG_BATCH_WAVES_HI from 6 points up)
+template <int N, int GK>
+constexpr int batch_waves()
+{
+  constexpr int cap = N >= 6 ? DG_BATCH_WAVES_HI : DG_BATCH_WAVES;
+  constexpr int occ = Occupancy<N, float>::value;
+  return occ < cap ? occ : cap;
+}
+template <int N, int GK>
+constexpr int kBatchWaves = batch_waves<N, GK>();
 
 // device descriptor of one active request
 struct BatchSlot {
@@ -103,37 +110,30 @@ __device__ __forceinline__ T *as_global(T *p)
   return (T *)(GT *)(uintptr_t)p;
 }
 
-// the apply of one item, inlined into its degree's persistent kernel
-template <int N>
-__device__ __forceinline__ void batch_apply_one(const BatchSlot &sl, int blk, float *smem)
+// the storages a request's FP32 data can have, in descriptor order
+constexpr int kBatchKinds = 5;
+constexpr int kBatchKind[kBatchKinds] = {AFFINE_CONST, AFFINE_VAR, CURVED, CURVED_MERGED, CURVED_POS};
+inline int batch_kind_index(int gk)
 {
-  const OpView<float> &v = sl.v;
-  const float *p = as_global(sl.p);
-  float *q = as_global(sl.q);
-  const DotOut<float> dot{as_global(sl.share)};
-  switch (sl.gk) {
-    case CURVED: apply_batch<N, float, CURVED, kBatchTpb<N>, true>(v, p, q, blk, smem, dot); break;
-    case CURVED_MERGED: apply_batch<N, float, CURVED_MERGED, kBatchTpb<N>, true>(v, p, q, blk, smem, dot); break;
-    case CURVED_POS: apply_batch<N, float, CURVED_POS, kBatchTpb<N>, true>(v, p, q, blk, smem, dot); break;
-    case AFFINE_VAR: apply_batch<N, float, AFFINE_VAR, kBatchTpb<N>, true>(v, p, q, blk, smem, dot); break;
-    default: apply_batch<N, float, AFFINE_CONST, kBatchTpb<N>, true>(v, p, q, blk, smem, dot); break;
-  }
+  for (int g = 0; g < kBatchKinds; ++g)
+    if (kBatchKind[g] == gk) return g;
+  return -1;
 }
 
-// Persistent and XCD-aware, one kernel per degree: the kernel for N walks
-// the items [item_begin, item_end) of the requests of that degree (the
-// descriptors are ordered by degree, so these are contiguous).
-// Workgroups are dispatched to the 8 XCDs round robin (workgroup b to XCD
-// b mod 8), so the range is cut into 8 contiguous pieces and the G/8
-// workgroups of XCD x walk piece x with stride G/8: neighbouring cell
-// batches, which share neighbour blocks and face geometry, then run at about
-// the same time on one XCD and meet in its L2.  G is a multiple of 8; every
-// workgroup leaves its loop at the end of its piece.  One kernel per degree
-// (rather than one kernel calling a function per degree) keeps the apply
-// inlined: a call would save and restore the callee-saved registers through
-// scratch memory on every item.
-template <int N>
-__global__ void __launch_bounds__(kBatchTpb<N>, (kBatchWaves<N>))
+// Persistent and XCD-aware, one kernel per degree and storage: the kernel
+// for (N, GK) walks the items [item_begin, item_end) of the requests of that
+// degree and storage (the descriptors are ordered by both, so these are
+// contiguous).  Workgroups are dispatched to the 8 XCDs round robin
+// (workgroup b to XCD b mod 8), so the range is cut into 8 contiguous pieces
+// and the G/8 workgroups of XCD x walk piece x with stride G/8: neighbouring
+// cell batches, which share neighbour blocks and face geometry, then run at
+// about the same time on one XCD and meet in its L2.  G is a multiple of 8;
+// every workgroup leaves its loop at the end of its piece.  The apply is
+// inlined (a call would save and restore the callee-saved registers through
+// scratch memory on every item), and a kernel holds one storage's code only,
+// so that its register count is that storage's and not the largest one's.
+template <int N, int GK>
+__global__ void __launch_bounds__(kBatchTpb<N>, (kBatchWaves<N, GK>))
 batch_apply_kernel(const BatchSlot *__restrict__ slots, int nslots, int slot0, int item_begin, int item_end)
 {
   __shared__ float smem[kBatchLds<N>];
@@ -146,7 +146,9 @@ batch_apply_kernel(const BatchSlot *__restrict__ slots, int nslots, int slot0, i
     int s = slot0;
     while (s + 1 < nslots && slots[s + 1].item0 <= item) ++s;
     const BatchSlot &sl = slots[s];
-    batch_apply_one<N>(sl, item - sl.item0, smem);
+    const DotOut<float> dot{as_global(sl.share)};
+    apply_batch<N, float, GK, kBatchTpb<N>, true>(sl.v, as_global(sl.p), as_global(sl.q), item - sl.item0, smem,
+                                                  dot);
     __syncthreads();
   }
 }
@@ -222,8 +224,10 @@ struct dg_batch {
   std::vector<int> active;   // request index per descriptor position (ordered by degree)
   std::vector<int> refreshing;   // descriptor positions taking a refinement step this round
   int nitems = 0;
-  // per number of points n: descriptors [slot0[n], ...) and items [item0[n], item1[n])
-  int slot0[kBatchMaxN + 1] = {}, item0[kBatchMaxN + 1] = {}, item1[kBatchMaxN + 1] = {};
+  // per number of points n and storage g (kBatchKind): descriptors
+  // [slot0[n][g], ...) and items [item0[n][g], item1[n][g])
+  int slot0[kBatchMaxN + 1][kBatchKinds] = {}, item0[kBatchMaxN + 1][kBatchKinds] = {},
+      item1[kBatchMaxN + 1][kBatchKinds] = {};
 };
 
 namespace {
@@ -301,13 +305,14 @@ dg_status rebuild(dg_batch *b, hipStream_t s)
 {
   b->active.clear();
   int item = 0;
-  // descriptors ordered by degree, so that each degree's items are contiguous
-  for (int n = kBatchMinN; n <= kBatchMaxN; ++n) {
-    b->slot0[n] = (int)b->active.size();
-    b->item0[n] = item;
+  // descriptors ordered by degree and storage, so that the items of each
+  // (degree, storage) are contiguous
+  for (int n = kBatchMinN; n <= kBatchMaxN; ++n) for (int g = 0; g < kBatchKinds; ++g) {
+    b->slot0[n][g] = (int)b->active.size();
+    b->item0[n][g] = item;
     for (int i = 0; i < b->max_slots; ++i) {
       Request &r = b->req[i];
-      if (!r.used || r.done || r.op->n != n) continue;
+      if (!r.used || r.done || r.op->n != n || batch_kind_index(r.op->gk32) != g) continue;
       BatchSlot &d = b->h_desc[b->active.size()];
       const int cells_per_item = batch_tpb(n) / (n * n);
       d.v = r.op->v32;
@@ -327,7 +332,7 @@ dg_status rebuild(dg_batch *b, hipStream_t s)
       item += d.nitems;
       b->active.push_back(i);
     }
-    b->item1[n] = item;
+    b->item1[n][g] = item;
   }
   b->nitems = item;
   if (!b->active.empty()) {
@@ -336,6 +341,21 @@ dg_status rebuild(dg_batch *b, hipStream_t s)
   }
   b->dirty = false;
   return DG_OK;
+}
+
+// the persistent apply of the requests with N points and storage kBatchKind[g]
+template <int N>
+void launch_batch_apply(int g, int grid, const dg_batch *b, int na, hipStream_t s)
+{
+  const int a0 = b->slot0[N][g], a1 = b->item0[N][g], a2 = b->item1[N][g];
+  const dim3 gd(grid), bd(kBatchTpb<N>);
+  switch (kBatchKind[g]) {
+    case AFFINE_CONST: hipLaunchKernelGGL((batch_apply_kernel<N, AFFINE_CONST>), gd, bd, 0, s, b->d_desc, na, a0, a1, a2); break;
+    case AFFINE_VAR: hipLaunchKernelGGL((batch_apply_kernel<N, AFFINE_VAR>), gd, bd, 0, s, b->d_desc, na, a0, a1, a2); break;
+    case CURVED: hipLaunchKernelGGL((batch_apply_kernel<N, CURVED>), gd, bd, 0, s, b->d_desc, na, a0, a1, a2); break;
+    case CURVED_MERGED: hipLaunchKernelGGL((batch_apply_kernel<N, CURVED_MERGED>), gd, bd, 0, s, b->d_desc, na, a0, a1, a2); break;
+    default: hipLaunchKernelGGL((batch_apply_kernel<N, CURVED_POS>), gd, bd, 0, s, b->d_desc, na, a0, a1, a2); break;
+  }
 }
 
 }  // namespace
@@ -392,6 +412,7 @@ dg_status dg_batch_admit(dg_batch *b, dg_op *op, dg_vec bv, dg_vec xv, const dg_
     return fail(DG_ERR_ARG, "b and x must be FP64 vectors of length dg_n_dofs");
   if (bv.data == xv.data) return fail(DG_ERR_ARG, "b and x alias");
   if (op->n < kBatchMinN || op->n > kBatchMaxN) return fail(DG_ERR_UNSUPPORTED, "batched solves serve degrees 2..7");
+  if (batch_kind_index(op->gk32) < 0) return fail(DG_ERR_UNSUPPORTED, "no batched apply for this geometry storage");
   if (!(prm->rel_tol > 0) || !(prm->rel_tol_inner > 0 && prm->rel_tol_inner < 1) || prm->max_iter < 1 ||
       prm->check_every < 1)
     return fail(DG_ERR_ARG, "bad solver parameters (rel_tol > 0, 0 < rel_tol_inner < 1, max_iter, check_every >= 1)");
@@ -482,20 +503,19 @@ dg_status dg_batch_run(dg_batch *b, int max_rounds, void *stream)
     const int na = (int)b->active.size();
     if (na == 0) break;
     b->round += 1;
-    for (int n = kBatchMinN; n <= kBatchMaxN; ++n) {
-      const int items = b->item1[n] - b->item0[n];
+    for (int n = kBatchMinN; n <= kBatchMaxN; ++n) for (int g = 0; g < kBatchKinds; ++g) {
+      const int items = b->item1[n][g] - b->item0[n][g];
       if (items == 0) continue;
       // a multiple of the XCD count, at most DG_BATCH_GRID
       const int want = items < DG_BATCH_GRID ? items : DG_BATCH_GRID;
       const int grid = ((want + kXcds - 1) / kXcds) * kXcds;
-      const int args[3] = {b->slot0[n], b->item0[n], b->item1[n]};
       switch (n) {
-        case 3: hipLaunchKernelGGL(batch_apply_kernel<3>, dim3(grid), dim3(kBatchTpb<3>), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
-        case 4: hipLaunchKernelGGL(batch_apply_kernel<4>, dim3(grid), dim3(kBatchTpb<4>), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
-        case 5: hipLaunchKernelGGL(batch_apply_kernel<5>, dim3(grid), dim3(kBatchTpb<5>), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
-        case 6: hipLaunchKernelGGL(batch_apply_kernel<6>, dim3(grid), dim3(kBatchTpb<6>), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
-        case 7: hipLaunchKernelGGL(batch_apply_kernel<7>, dim3(grid), dim3(kBatchTpb<7>), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
-        default: hipLaunchKernelGGL(batch_apply_kernel<8>, dim3(grid), dim3(kBatchTpb<8>), 0, s, b->d_desc, na, args[0], args[1], args[2]); break;
+        case 3: launch_batch_apply<3>(g, grid, b, na, s); break;
+        case 4: launch_batch_apply<4>(g, grid, b, na, s); break;
+        case 5: launch_batch_apply<5>(g, grid, b, na, s); break;
+        case 6: launch_batch_apply<6>(g, grid, b, na, s); break;
+        case 7: launch_batch_apply<7>(g, grid, b, na, s); break;
+        default: launch_batch_apply<8>(g, grid, b, na, s); break;
       }
     }
     hipLaunchKernelGGL(batch_shares_kernel, dim3(na), dim3(kSumThreads), 0, s, b->d_desc);
