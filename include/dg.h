@@ -345,9 +345,10 @@ dg_status dg_tables(int degree, double *out, size_t len);
  * requests (mixed precision with reliable updates, the scheme of
  * dg_cg_solve mode 2).  dg_batch_run advances every active slot by one CG
  * iteration per round.  A round is a fixed sequence of launches: per degree
- * present, ONE persistent apply kernel whose workgroups walk a work list of
- * (slot, cell batch) items covering the cell lists of all active requests
- * of that degree, whatever their size and geometry; then kernels that
+ * and FP32 geometry storage present, ONE persistent apply kernel whose
+ * workgroups walk a work list of (slot, cell batch) items covering the cell
+ * lists of all active requests of that degree and storage, whatever their
+ * size; then kernels that
  * reduce and update the vectors of all active requests together.  Requests
  * may be admitted while others run.  Results do not depend on which other
  * requests share the batch: every reduction of a request is done over a

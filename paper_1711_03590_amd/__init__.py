@@ -474,9 +474,9 @@ class Batch:
     """Continuous batching of mixed-precision solves (dg_batch_* of the C ABI).
 
     Requests are admitted into free slots at any time; run(rounds) advances
-    every active request by that many CG iterations with one persistent
-    apply launch (plus three batched BLAS launches) per iteration; poll()
-    returns the requests that finished."""
+    every active request by that many CG iterations, each one persistent
+    apply launch per degree and geometry storage present plus three batched
+    vector launches; poll() returns the requests that finished."""
 
     def __init__(self, max_slots, torch_alloc=True):
         self._alloc = TorchAllocator() if torch_alloc else None

@@ -3,10 +3,10 @@
 // A batch holds up to max_slots requests, each a reliable-update mixed CG
 // (dg_cg_solve mode 2) on its own operator.  dg_batch_run advances all
 // active requests by one CG iteration per round; a round is:
-//   1. per degree present, one persistent apply kernel whose workgroups walk
-//      a list of (request, cell batch) items spanning every active request
-//      of that degree, whatever its size or geometry (q = A p in FP32, and
-//      each item's share of p.q);
+//   1. per degree and FP32 geometry storage present, one persistent apply
+//      kernel whose workgroups walk a list of (request, cell batch) items
+//      spanning every active request of that degree and storage, whatever
+//      its size (q = A p in FP32, and each item's share of p.q);
 //   2. the sum of each request's p.q shares, in item order;
 //   3.-4. two batched BLAS kernels over (request, chunk) items of all
 //      requests: the x/r update with r.z, r.r partials, and the p update.
