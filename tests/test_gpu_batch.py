@@ -181,3 +181,23 @@ def test_serve_small_trace(dg, orc):
         p = orc.problem(d["ncell"], d["degree"], curved=d["curved"])
         res = np.linalg.norm(d["b"] - orc.apply(p, d["x"])) / np.linalg.norm(d["b"])
         assert res <= 2e-8, f"served request {d['id']}: oracle residual {res:.3e}"
+
+
+def test_serve_lanes_bitwise(dg):
+    """The same small trace served with one lane and with three: every
+    request's solution is bitwise the same, since nothing in a request's
+    solve depends on which lane or which other requests it shares the GPU
+    with (streams, batches, admission order)."""
+    from paper_1711_03590_amd import serve
+    trace = synth.request_trace(12, rate=400.0, seed=11, edge_range=(3, 8))
+    budget = 3 * max(serve.request_bytes(r)[0] for r in trace)
+    out = {}
+    for lanes in (1, 3):
+        seen = []
+        rep = serve.serve(trace, budget_bytes=budget, max_slots=6, rounds_per_step=5, rel_tol=1e-8,
+                          log=seen.append, keep=lambda r: True, lanes=lanes)
+        assert rep["completed"] == 12 and rep["all_converged"] and rep["lanes"] == lanes
+        out[lanes] = {d["id"]: d["x"] for d in seen}
+    assert out[1].keys() == out[3].keys()
+    for i in out[1]:
+        assert np.array_equal(out[1][i], out[3][i]), f"request {i}: lanes change the solution"
