@@ -75,15 +75,15 @@ template <int N>
 constexpr int kBatchLds = batch_lds<N>();
 // occupancy target (waves per SIMD) given to the compiler: the stand-alone
 // apply's, at most DG_BATCH_WAVES (DG_BATCH_WAVES_HI from 6 points up)
-template <int N, int GK>
+template <int N>
 constexpr int batch_waves()
 {
   constexpr int cap = N >= 6 ? DG_BATCH_WAVES_HI : DG_BATCH_WAVES;
   constexpr int occ = Occupancy<N, float>::value;
   return occ < cap ? occ : cap;
 }
-template <int N, int GK>
-constexpr int kBatchWaves = batch_waves<N, GK>();
+template <int N>
+constexpr int kBatchWaves = batch_waves<N>();
 
 // device descriptor of one active request
 struct BatchSlot {
@@ -133,7 +133,7 @@ inline int batch_kind_index(int gk)
 // scratch memory on every item), and a kernel holds one storage's code only,
 // so that its register count is that storage's and not the largest one's.
 template <int N, int GK>
-__global__ void __launch_bounds__(kBatchTpb<N>, (kBatchWaves<N, GK>))
+__global__ void __launch_bounds__(kBatchTpb<N>, (kBatchWaves<N>))
 batch_apply_kernel(const BatchSlot *__restrict__ slots, int nslots, int slot0, int item_begin, int item_end)
 {
   __shared__ float smem[kBatchLds<N>];
