@@ -80,11 +80,33 @@ def test_validation_without_device(dg):
         dg.footprint(2000, 4)   # more than 2^31-1 DoFs
 
 
+def _apply_threads(n):
+    """Threads of an apply workgroup: two waves, or one where whole cells of
+    n^2 lines fill one wave as well as two."""
+    n2 = n * n
+    base = 128 if n2 <= 128 else -(-n2 // 64) * 64
+    if n2 <= 64 and (64 // n2) * n2 * base == (base // n2) * n2 * 64:
+        return 64
+    return base
+
+
 def _geo_cells(cells, n):
     """Cells the stored cell-geometry arrays hold: padded to whole groups of
-    one apply workgroup's cells (128 threads, n^2 per cell)."""
-    g = 128 // (n * n)
+    one apply workgroup's cells (n^2 threads per cell)."""
+    g = _apply_threads(n) // (n * n)
     return -(-cells // g) * g
+
+
+def test_geometry_groups_per_degree(dg):
+    # one-wave workgroups at 2, 3, 4, 7 and 8 points (16, 7, 4, 1, 1 cells),
+    # two waves at 5 and 6 (5 and 3 cells), and 128 threads, one cell, at 9
+    assert [_apply_threads(n) // (n * n) for n in range(2, 10)] == [16, 7, 4, 5, 3, 1, 1, 1]
+    for k, N in ((2, 10), (1, 5), (6, 3), (5, 7)):
+        n = k + 1
+        cells = N ** 3
+        faces = 3 * N * N * (N + 1)
+        vals = 10 * _geo_cells(cells, n) * n ** 3 + 4 * faces * n ** 2
+        assert dg.footprint(N, k, curved=True, precisions=dg.PREC_F64) == vals * 8 + cells * n ** 3 * 8
 
 
 def test_footprint_counts(dg):
