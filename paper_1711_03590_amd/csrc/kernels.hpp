@@ -643,17 +643,21 @@ __device__ __forceinline__ Real wg_sum(Real v, Real *sh)
 }
 
 // The fused pass over the cells of one batch (cells blk*B .. blk*B+B-1) by
-// a workgroup of TPB threads; smem holds B * (2 N^3 + WSZ) values.
+// a workgroup of TPB threads; smem holds B * (2 N^3 + WSZ) values.  tid is
+// the thread's index in the workgroup (threadIdx.x when negative); a caller
+// that applies several batches in a loop passes it redefined per batch, so
+// that what the pass derives from it is not hoisted out of the loop and
+// kept live across it.
 template <int N, typename Real, int GK, int TPB, bool DOT = false, int BS = BASIS_NODAL, bool GH = false>
 __device__ __forceinline__ void apply_batch(const OpView<Real> &op, const Real *__restrict__ src,
                                             Real *__restrict__ dst, int blk, Real *smem,
-                                            const DotOut<Real> &dot = DotOut<Real>{})
+                                            const DotOut<Real> &dot = DotOut<Real>{}, int tid = -1)
 {
   using BK = Blocking<N, TPB>;
   constexpr int N2 = BK::N2, N3 = BK::N3, B = BK::B, NT = BK::NT, WSZ = BK::WSZ;
   constexpr Tables<N> T = kTab<N>;
 
-  const int t = threadIdx.x;
+  const int t = tid >= 0 ? tid : (int)threadIdx.x;
   const bool act = t < NT;
   const int cb = act ? t / N2 : 0;
   const int l = act ? t - cb * N2 : 0;
