@@ -346,12 +346,14 @@ def main():
                     help="run only this geometry in the 64^3 comparison (variants leg)")
     ap.add_argument("--solve-reps", type=int, default=20,
                     help="repeated config-4 solves per mode for the latency percentiles (0: skip)")
-    ap.add_argument("--serve-requests", type=int, default=200,
+    ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests in the serving trace (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-budget-gib", type=float, default=128.0, help="HBM admission budget")
     ap.add_argument("--serve-low-rate", type=float, default=10.0,
                     help="arrival rate of a second, lighter trace (0: skip)")
+    ap.add_argument("--serve-low-requests", type=int, default=100,
+                    help="requests in the lighter trace")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -440,7 +442,7 @@ def main():
     if "serve" in legs:
         serving = bench_serve(synth, args.serve_requests, args.serve_rate, args.serve_budget_gib)
         if args.serve_low_rate > 0:
-            serving["below_capacity"] = bench_serve(synth, max(20, args.serve_requests // 2), args.serve_low_rate,
+            serving["below_capacity"] = bench_serve(synth, args.serve_low_requests, args.serve_low_rate,
                                                     args.serve_budget_gib, keep_smallest=0)
         out["serve"] = serving
 
