@@ -129,8 +129,8 @@ def test_alone_equals_mix_equals_single_solve(dg, orc, alone):
         res = np.linalg.norm(bh - orc.apply(p, x_mix.cpu().numpy())) / np.linalg.norm(bh)
         assert res <= 2 * TOL, f"request {i} in the mix: oracle residual {res:.3e}"
     # and the single-request solver in its reliable-update mode: the same
-    # method, but its p.(A p) comes out of the apply (workgroup partials in
-    # another grouping), so the two agree to the solver tolerance
+    # method through other kernels (the stand-alone apply and BLAS steps),
+    # held to the solver tolerance
     for i, (op, b, x, st) in enumerate(alone):
         xs, sts = op.cg_solve(b, mode=2, rel_tol=TOL, rel_tol_inner=0.3, check_every=10)
         assert sts["converged"]
