@@ -40,6 +40,18 @@ def request_bytes(req):
             + WORKSPACE_BYTES_PER_DOF * n, n)
 
 
+def _materialize(req, stream):
+    """The request's operator (built on `stream`), its seeded right-hand side
+    and a zero initial guess, on the GPU."""
+    import torch
+    op = Operator(req["ncell"], req["degree"], curved=req["curved"], storage=STORAGE, stream=stream)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(req["rhs_seed"])
+    b = torch.rand(op.n_dofs, dtype=torch.float64, device="cuda", generator=g) * 2.0 - 1.0
+    x = torch.zeros_like(b)
+    return op, b, x
+
+
 class _Lane:
     """One batch on its own stream.  Only the lane's driving thread touches
     the batch: the admitting thread hands it requests through its inbox."""
@@ -78,11 +90,7 @@ def serve(trace, *, budget_bytes, max_slots=32, rounds_per_step=10, rel_tol=1e-8
     errors = []
 
     def admit(lane, req, need, ndofs):
-        op = Operator(req["ncell"], req["degree"], curved=req["curved"], storage=STORAGE, stream=lane.stream)
-        g = torch.Generator(device="cuda")
-        g.manual_seed(req["rhs_seed"])
-        b = torch.rand(op.n_dofs, dtype=torch.float64, device="cuda", generator=g) * 2.0 - 1.0
-        x = torch.zeros_like(b)
+        op, b, x = _materialize(req, lane.stream)
         slot = lane.batch.admit(op, b, x, rel_tol=rel_tol, stream=lane.stream)
         lane.recs[slot] = dict(req=req, op=op, b=b, x=x, need=need, ndofs=ndofs,
                                admitted=time.perf_counter() - t0)
