@@ -810,7 +810,7 @@ def bench_serve(synth, n_requests, rate, budget_gib, keep_smallest=3):
     small = sorted(trace, key=lambda r: serve.request_bytes(r)[1])[:keep_smallest]
     keep_ids = {r["id"] for r in small}
     kept = []
-    rep = serve.serve(trace, budget_bytes=int(budget_gib * (1 << 30)), max_slots=48, rounds_per_step=10,
+    rep = serve.serve(trace, budget_bytes=int(budget_gib * (1 << 30)), max_slots=48, rounds_per_step=20,
                       rel_tol=1e-8, keep=lambda r: r["id"] in keep_ids,
                       log=lambda d: kept.append(d) if "x" in d else None)
     rep["workload"] = (f"{n_requests} requests, Poisson arrivals at {rate:g}/s, edge cells log-uniform in [4,48], "

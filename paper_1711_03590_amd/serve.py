@@ -65,7 +65,7 @@ class _Lane:
         self.wake = threading.Event()     # set when a request is assigned
 
 
-def serve(trace, *, budget_bytes, max_slots=32, rounds_per_step=10, rel_tol=1e-8, time_limit=None, log=None,
+def serve(trace, *, budget_bytes, max_slots=48, rounds_per_step=20, rel_tol=1e-8, time_limit=None, log=None,
           keep=None, lanes=4):
     """Serve `trace` (dicts with arrival, ncell, degree, curved, rhs_seed)
     over `lanes` batches on their own streams, with at most max_slots
