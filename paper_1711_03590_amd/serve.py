@@ -11,8 +11,9 @@ thread (lane 0 by the thread that also admits requests): the lanes' kernels
 overlap on the GPU, so that one lane's bandwidth-bound vector updates run
 beside another lane's applies, and one lane's host work (residual checks,
 refinement steps, retiring finished requests) beside the others' GPU work.
-A request joins the lane with the fewest resident DoFs among those free to
-take it at that moment.  Latency is completion time minus arrival time.
+A request is handed to the lane with the fewest DoFs assigned to it, whose
+thread builds its operator and admits it between two of its steps.
+Latency is completion time minus arrival time.
 Curved operators keep the stored Jacobians for their FP64 residuals and the
 merged coefficient for the FP32 inner solver (the mixed geometry storage),
 which is the cheaper resident footprint and the faster inner apply.
